@@ -1,0 +1,178 @@
+/*
+ * ccc.h -- C ABI of the MI355X (gfx950) Custom Correlation Coefficient tally
+ * library (Joubert et al., "Parallel Accelerated Custom Correlation
+ * Coefficient Calculations for Genomics Applications").
+ *
+ * Problem statement (Sec. 2.1): n_v vectors of n_f entries; each entry is a
+ * pair of alleles from {0,1}.  rho_{i,q}(a) is the number of alleles of entry
+ * (i,q) equal to a.  The library computes, for every pair i<j (Sec. 2.1) or
+ * triple i<j<k (Sec. 2.2), the allele co-occurrence tables
+ *     C_ij(a,b)    = sum_q rho_{i,q}(a) rho_{j,q}(b)                 (Eq. (2))
+ *     C_ijk(a,b,c) = sum_q rho_{i,q}(a) rho_{j,q}(b) rho_{k,q}(c)    (Eq. (5))
+ * as exact integers, and the CCC values
+ *     CCC_ij(a,b)    = f_ij(a,b) (1 - g f_i(a)) (1 - g f_j(b))       (Eq. (3))
+ *     CCC_ijk(a,b,c) = f_ijk(a,b,c) (1-g f_i(a)) (1-g f_j(b)) (1-g f_k(c)) (Eq. (4))
+ * in double precision, with f_i(a) = n_i(a) / (2 m_i) (Eq. (1)),
+ * f_ij = C_ij / (4 m_ij), f_ijk = C_ijk / (8 m_ijk).
+ *
+ * Input layout (all entry points): packed rows, uint8 v[n][ld], ld % 16 == 0,
+ * ld >= ceil(n_f/4).  Field q of vector i sits at bits 2(q%4) (low) and
+ * 2(q%4)+1 (high) of byte i*ld + q/4; the 2-bit code is the allele pair, high
+ * bit first: 00 = (0,0), 01 = (0,1), 11 = (1,1), and 10 = (1,0) marks a
+ * missing entry (the marker the paper's future-work section sets aside).  Bits
+ * past n_f are ignored whatever they hold.  Only the first ceil(n_f/4) bytes
+ * of each row, rounded up to a multiple of 16, are ever read, so a row pointer
+ * may point into a wider row (a field chunk) whose stride is ld.
+ *
+ * Missing data: a missing entry contributes to no tally; m_i counts the
+ * present fields of vector i, m_ij (m_ijk) the fields where every vector of
+ * the pair (triple) is present -- so m_ij = sum C_ij / 4 and m_ijk = sum C_ijk
+ * / 8.  With no missing data these all equal n_f, the paper's normaliser.  A
+ * zero m_i gives f_i = 0; a zero m_ij (m_ijk) gives CCC = 0 for the pair
+ * (triple).
+ *
+ * Output layouts: table entry order is 2a+b (2-way) and 4a+2b+c (3-way), a
+ * belonging to the smallest vector index.  Pairs i<j are stored at
+ *     p(i,j) = i*n_v - i(i+1)/2 + (j-i-1)                     (lexicographic),
+ * triples i<j<k at their lexicographic rank
+ *     C(n_v,3) - C(n_v-i,3) + C(n_v-i-1,2) - C(n_v-j,2) + (k-j-1).
+ * Per-vector counts are int32 [n][4] = (n_i(0), n_i(1), m_i, 0).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers owned by the caller, 16-byte
+ *    aligned.  The library never frees them.
+ *  - Work is enqueued on `stream` (NULL = the default stream) and returns
+ *    without waiting for it.
+ *  - A negative return code comes from argument validation done before any
+ *    work is enqueued; outputs are then untouched.  CCC_ERR_HIP means a HIP
+ *    call or launch failed after validation.
+ *  - The library keeps a per-device workspace (allocated on first need,
+ *    grown on demand, released by ccc_release_workspace).  Calls are
+ *    reentrant per stream; calls on different streams of one device that
+ *    need the workspace must be ordered by the caller.
+ */
+#ifndef CCC_H
+#define CCC_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  CCC_OK = 0,
+  CCC_ERR_ARG = -1,         /* null pointer, negative size, bad option, ld < ceil(n_f/4) */
+  CCC_ERR_RANGE = -2,       /* a table entry could exceed INT32_MAX (see each call) */
+  CCC_ERR_ALIGN = -3,       /* pointer not 16-byte aligned or ld % 16 != 0 */
+  CCC_ERR_HIP = -4,         /* a HIP call or kernel launch failed */
+  CCC_ERR_NOMEM = -5,       /* workspace allocation failed */
+  CCC_ERR_UNSUPPORTED = -6  /* no gfx950 device / feature not available */
+};
+
+/* Computation paths.  Both give bit-identical tables. */
+enum {
+  CCC_PATH_AUTO = 0,      /* int8 MFMA */
+  CCC_PATH_POPCOUNT = 1,  /* bitwise AND + population count (the paper's tally form, Sec. 3.1) */
+  CCC_PATH_MFMA = 2       /* per-allele counts {0,1,2} as int8 MFMA operands, int32 accumulation */
+};
+
+/* Flags for ccc_2way_block (field-chunked use). */
+enum {
+  CCC_ACCUMULATE = 1u, /* add this chunk into tables and counts instead of overwriting */
+  CCC_FINALIZE = 2u    /* this is the last chunk: write CCC values */
+};
+
+typedef struct {
+  int path;       /* CCC_PATH_* */
+  double gamma;   /* the constant of Eqs. (3)-(4); the paper uses 2/3 */
+  unsigned flags; /* CCC_ACCUMULATE | CCC_FINALIZE (ccc_2way_block only) */
+} ccc_opts;
+
+/* Options used when `opts` is NULL: CCC_PATH_AUTO, gamma = 2/3, flags 0. */
+ccc_opts ccc_default_opts(void);
+
+/*
+ * ccc_2way -- all pairs i<j of one vector set (Sec. 2.1, Eqs. (1)-(3)).
+ *   v       [n_v][ld] packed input.
+ *   tables  int32 [n_v(n_v-1)/2][4] or NULL; written.
+ *   ccc     double [n_v(n_v-1)/2][4] or NULL; written.  At least one of
+ *           tables / ccc must be non-NULL.
+ *   counts  int32 [n_v][4] or NULL; if given, the 1-way counts are written.
+ * n_v < 2 is valid and writes no tables (counts are written when n_v == 1).
+ * n_f == 0 writes all-zero tables and CCC.  CCC_ERR_RANGE if 4*n_f >
+ * INT32_MAX.  opts->flags must be 0.
+ */
+int ccc_2way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream);
+
+/*
+ * ccc_3way -- all triples i<j<k of one vector set (Sec. 2.2, Eqs. (4)-(5)).
+ *   tables  int32 [C(n_v,3)][8] or NULL;  ccc double [C(n_v,3)][8] or NULL
+ *   (at least one non-NULL);  counts as for ccc_2way.
+ * n_v < 3 writes no tables.  CCC_ERR_RANGE if 8*n_f > INT32_MAX.
+ * The path option selects the MFMA or popcount kernel.
+ */
+int ccc_3way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream);
+
+/*
+ * ccc_2way_block -- every pair (i in A, j in B) of two vector sets: one
+ * off-diagonal block of the paper's block decomposition of the 2-way result
+ * matrix (Sec. 4), over one chunk of fields (the field axis of Sec. 4, whose
+ * partial tallies are reduced by summation).
+ *   va [n_a][lda], vb [n_b][ldb]: packed fields of this chunk (n_f of them).
+ *   tables   int32 [n_a][n_b][4], row-major, required.  Overwritten, or added
+ *            to with CCC_ACCUMULATE.
+ *   counts_a int32 [n_a][4], counts_b int32 [n_b][4], required; overwritten,
+ *            or added to with CCC_ACCUMULATE.
+ *   ccc      double [n_a][n_b][4]; written only with CCC_FINALIZE (then
+ *            required), from the (accumulated) tables and counts.
+ * A sequence of calls over consecutive field chunks, the first without
+ * CCC_ACCUMULATE, the rest with it, and the last with CCC_FINALIZE, gives the
+ * same tables, counts and CCC as one call over all fields.  CCC_ERR_RANGE if
+ * 4*n_f > INT32_MAX for this chunk; keeping the accumulated total within
+ * range is the caller's duty (the counts' m_i bound it).  n_a or n_b == 0 is
+ * valid and writes nothing.
+ */
+int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* vb, int64_t n_b,
+                   int64_t ldb, int64_t n_f, int32_t* tables, int32_t* counts_a,
+                   int32_t* counts_b, double* ccc, const ccc_opts* opts, hipStream_t stream);
+
+/* One independent 2-way problem for ccc_2way_many (same meaning as ccc_2way). */
+typedef struct {
+  const uint8_t* v;
+  int64_t n_v, n_f, ld;
+  int32_t* tables;
+  double* ccc;
+  int32_t* counts;
+} ccc_problem;
+
+/*
+ * ccc_2way_many -- many independent 2-way problems of uneven n_v and n_f in
+ * one persistent launch.  `probs` is a HOST array of n_probs descriptors
+ * (device pointers inside).  Each problem gives exactly what ccc_2way would.
+ * The launch sequence is captured once into a HIP graph per distinct batch
+ * (same descriptors) and replayed on later calls with that batch.
+ * Validation covers every problem before anything is enqueued.
+ */
+int ccc_2way_many(const ccc_problem* probs, int n_probs, const ccc_opts* opts,
+                  hipStream_t stream);
+
+/* Static text for a status code. */
+const char* ccc_status_string(int status);
+
+/* Free the workspace and cached graphs of every device (waits for the device). */
+void ccc_release_workspace(void);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int ccc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCC_H */

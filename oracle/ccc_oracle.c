@@ -35,6 +35,9 @@
  * Packed input: uint8 v[n][ld]; field q at bits 2(q%4) and 2(q%4)+1 of byte
  * q/4; the 2-bit code is the allele pair (high bit, low bit).
  *
+ * Loops run over the first index serially and over the second in parallel
+ * (OpenMP), so a single sampled row uses every core.
+ *
  * Whole-output checksums (the paper's exact checksum idea, Sec. 5) are
  * weighted sums mod the prime 2^61-1; the *_from_input forms evaluate the same
  * sum through a reordering that needs only O(n_v n_f) work.
@@ -147,9 +150,9 @@ void oracle_2way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, in
                       double* ccc) {
   if (i0 >= i1) return;
   int64_t base = oracle_pair_index(n_v, i0, i0 + 1);
-#pragma omp parallel for schedule(dynamic)
   for (int64_t i = i0; i < i1; ++i) {
     const uint8_t* ri = v + i * ld;
+#pragma omp parallel for schedule(static)
     for (int64_t j = i + 1; j < n_v; ++j) {
       const uint8_t* rj = v + j * ld;
       int64_t t[4] = {0, 0, 0, 0};
@@ -174,9 +177,9 @@ void oracle_block_rows(const uint8_t* va, int64_t lda, const uint8_t* vb, int64_
                        int64_t ldb, int64_t n_f, int64_t a0, int64_t a1,
                        const int64_t* counts_a, const int64_t* counts_b, double gamma,
                        int64_t* tables, double* ccc) {
-#pragma omp parallel for schedule(dynamic)
   for (int64_t i = a0; i < a1; ++i) {
     const uint8_t* ri = va + i * lda;
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n_b; ++j) {
       const uint8_t* rj = vb + j * ldb;
       int64_t t[4] = {0, 0, 0, 0};
@@ -224,10 +227,9 @@ void oracle_3way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, in
                       double* ccc) {
   if (i0 >= i1 || n_v < 3) return;
   int64_t base = oracle_triple_index(n_v, i0, i0 + 1, i0 + 2);
-#pragma omp parallel for schedule(dynamic) collapse(2)
   for (int64_t i = i0; i < i1; ++i) {
-    for (int64_t j = 0; j < n_v; ++j) {
-      if (j <= i) continue;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t j = i + 1; j < n_v; ++j) {
       const uint8_t* ri = v + i * ld;
       const uint8_t* rj = v + j * ld;
       for (int64_t k = j + 1; k < n_v; ++k) {

@@ -1,0 +1,256 @@
+"""MI355X (gfx950) Custom Correlation Coefficient tallies: Python binding.
+
+Thin ctypes layer over ``libccc.so`` (C ABI in ``include/ccc.h``): it checks
+tensor dtypes/devices, allocates output tensors through PyTorch when the
+caller passes none, passes raw device pointers and the current HIP stream, and
+turns negative status codes into :class:`CccError`.  Every step of the
+computation runs in the library's HIP kernels; there is no fallback.
+
+Functions carry the C names: :func:`ccc_2way`, :func:`ccc_3way`,
+:func:`ccc_2way_block`, :func:`ccc_2way_many`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccc.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ccc.h")
+
+CCC_OK, CCC_ERR_ARG, CCC_ERR_RANGE, CCC_ERR_ALIGN = 0, -1, -2, -3
+CCC_ERR_HIP, CCC_ERR_NOMEM, CCC_ERR_UNSUPPORTED = -4, -5, -6
+CCC_PATH_AUTO, CCC_PATH_POPCOUNT, CCC_PATH_MFMA = 0, 1, 2
+CCC_ACCUMULATE, CCC_FINALIZE = 1, 2
+GAMMA = 2.0 / 3.0
+
+_PATHS = {"auto": CCC_PATH_AUTO, "popcount": CCC_PATH_POPCOUNT, "mfma": CCC_PATH_MFMA,
+          CCC_PATH_AUTO: CCC_PATH_AUTO, CCC_PATH_POPCOUNT: CCC_PATH_POPCOUNT,
+          CCC_PATH_MFMA: CCC_PATH_MFMA}
+
+
+class CccError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+class ccc_opts(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int), ("gamma", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+class ccc_problem(ctypes.Structure):
+    _fields_ = [("v", ctypes.c_void_p), ("n_v", ctypes.c_int64), ("n_f", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("tables", ctypes.c_void_p), ("ccc", ctypes.c_void_p),
+                ("counts", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libccc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1705_08213_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+        opts_p = ctypes.POINTER(ccc_opts)
+        L.ccc_2way.argtypes = [vp, i64, i64, i64, vp, vp, vp, opts_p, vp]
+        L.ccc_3way.argtypes = [vp, i64, i64, i64, vp, vp, vp, opts_p, vp]
+        L.ccc_2way_block.argtypes = [vp, i64, i64, vp, i64, i64, i64, vp, vp, vp, vp, opts_p, vp]
+        L.ccc_2way_many.argtypes = [ctypes.POINTER(ccc_problem), cint, opts_p, vp]
+        for f in (L.ccc_2way, L.ccc_3way, L.ccc_2way_block, L.ccc_2way_many):
+            f.restype = cint
+        L.ccc_status_string.argtypes = [cint]
+        L.ccc_status_string.restype = ctypes.c_char_p
+        L.ccc_version.restype = cint
+        L.ccc_default_opts.restype = ccc_opts
+        L.ccc_release_workspace.restype = None
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/ccc.h."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccc_[a-z0-9_]+)\s*\(", text)))
+
+
+def status_string(status: int) -> str:
+    return lib().ccc_status_string(status).decode()
+
+
+def version() -> int:
+    return lib().ccc_version()
+
+
+def release_workspace() -> None:
+    lib().ccc_release_workspace()
+
+
+def make_opts(path="auto", gamma=GAMMA, flags=0) -> ccc_opts:
+    """Options struct; ``path`` is a name or a raw integer (passed through, so
+    the library's own validation can be exercised)."""
+    p = _PATHS[path] if isinstance(path, str) else int(path)
+    return ccc_opts(p, float(gamma), int(flags))
+
+
+# ---------------------------------------------------------------------------
+# torch-facing wrappers
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_input(v, name="v"):
+    torch = _torch()
+    if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.uint8 and v.dim() == 2
+            and v.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous 2-D uint8 CUDA tensor [n, ld]")
+
+
+def _check_out(t, shape, dtype, name):
+    torch = _torch()
+    if t is None:
+        return
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and tuple(t.shape) == tuple(shape)):
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}")
+
+
+def _raise(st, where):
+    if st != CCC_OK:
+        raise CccError(st, where)
+
+
+def n_pairs(n: int) -> int:
+    return n * (n - 1) // 2 if n >= 2 else 0
+
+
+def n_triples(n: int) -> int:
+    return n * (n - 1) * (n - 2) // 6 if n >= 3 else 0
+
+
+def ccc_2way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
+             want_tables=True, want_ccc=True, stream=None):
+    """All pairs i<j: returns (tables int32 [P,4], ccc float64 [P,4], counts int32 [n_v,4])."""
+    torch = _torch()
+    _check_input(v)
+    n_v, ld = v.shape
+    P = n_pairs(n_v)
+    dev = v.device
+    if tables is None and want_tables:
+        tables = torch.empty((P, 4), dtype=torch.int32, device=dev)
+    if ccc is None and want_ccc:
+        ccc = torch.empty((P, 4), dtype=torch.float64, device=dev)
+    if counts is None:
+        counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
+    _check_out(tables, (P, 4), torch.int32, "tables")
+    _check_out(ccc, (P, 4), torch.float64, "ccc")
+    _check_out(counts, (n_v, 4), torch.int32, "counts")
+    o = make_opts(path, gamma)
+    st = lib().ccc_2way(_ptr(v), n_v, n_f, ld, _ptr(tables), _ptr(ccc), _ptr(counts),
+                        ctypes.byref(o), _stream(stream))
+    _raise(st, "ccc_2way")
+    return tables, ccc, counts
+
+
+def ccc_3way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
+             want_tables=True, want_ccc=True, stream=None):
+    """All triples i<j<k: returns (tables int32 [T,8], ccc float64 [T,8], counts)."""
+    torch = _torch()
+    _check_input(v)
+    n_v, ld = v.shape
+    T = n_triples(n_v)
+    dev = v.device
+    if tables is None and want_tables:
+        tables = torch.empty((T, 8), dtype=torch.int32, device=dev)
+    if ccc is None and want_ccc:
+        ccc = torch.empty((T, 8), dtype=torch.float64, device=dev)
+    if counts is None:
+        counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
+    _check_out(tables, (T, 8), torch.int32, "tables")
+    _check_out(ccc, (T, 8), torch.float64, "ccc")
+    _check_out(counts, (n_v, 4), torch.int32, "counts")
+    o = make_opts(path, gamma)
+    st = lib().ccc_3way(_ptr(v), n_v, n_f, ld, _ptr(tables), _ptr(ccc), _ptr(counts),
+                        ctypes.byref(o), _stream(stream))
+    _raise(st, "ccc_3way")
+    return tables, ccc, counts
+
+
+def ccc_2way_block(va, vb, n_f, tables, counts_a, counts_b, ccc=None, accumulate=False,
+                   finalize=True, path="auto", gamma=GAMMA, stream=None, field_offset=0):
+    """Every (i in A, j in B) over one field chunk; tables/counts are the
+    running state.  ``field_offset`` (bytes, a multiple of 16) selects the
+    chunk inside wider rows: the chunk starts at byte ``field_offset`` of each
+    row and the row stride stays ``v.shape[1]``."""
+    torch = _torch()
+    _check_input(va, "va")
+    _check_input(vb, "vb")
+    n_a, lda = va.shape
+    n_b, ldb = vb.shape
+    if field_offset % 16:
+        raise ValueError("field_offset must be a multiple of 16 bytes")
+    _check_out(tables, (n_a, n_b, 4), torch.int32, "tables")
+    _check_out(counts_a, (n_a, 4), torch.int32, "counts_a")
+    _check_out(counts_b, (n_b, 4), torch.int32, "counts_b")
+    _check_out(ccc, (n_a, n_b, 4), torch.float64, "ccc")
+    flags = (CCC_ACCUMULATE if accumulate else 0) | (CCC_FINALIZE if finalize else 0)
+    o = make_opts(path, gamma, flags)
+    pa = ctypes.c_void_p(va.data_ptr() + field_offset)
+    pb = ctypes.c_void_p(vb.data_ptr() + field_offset)
+    st = lib().ccc_2way_block(pa, n_a, lda, pb, n_b, ldb, n_f, _ptr(tables), _ptr(counts_a),
+                              _ptr(counts_b), _ptr(ccc), ctypes.byref(o), _stream(stream))
+    _raise(st, "ccc_2way_block")
+    return tables, ccc
+
+
+def ccc_2way_many(problems, path="auto", gamma=GAMMA, stream=None):
+    """``problems``: sequence of dicts with keys v, n_f and optional tables,
+    ccc, counts (outputs are allocated when absent).  Returns the list of
+    (tables, ccc, counts)."""
+    torch = _torch()
+    arr = (ccc_problem * max(len(problems), 1))()
+    outs = []
+    for k, p in enumerate(problems):
+        v = p["v"]
+        _check_input(v)
+        n_v, ld = v.shape
+        P = n_pairs(n_v)
+        t = p.get("tables")
+        c = p.get("ccc")
+        cnt = p.get("counts")
+        if t is None and p.get("want_tables", True):
+            t = torch.empty((P, 4), dtype=torch.int32, device=v.device)
+        if c is None and p.get("want_ccc", True):
+            c = torch.empty((P, 4), dtype=torch.float64, device=v.device)
+        if cnt is None:
+            cnt = torch.empty((n_v, 4), dtype=torch.int32, device=v.device)
+        _check_out(t, (P, 4), torch.int32, "tables")
+        _check_out(c, (P, 4), torch.float64, "ccc")
+        _check_out(cnt, (n_v, 4), torch.int32, "counts")
+        arr[k] = ccc_problem(v.data_ptr(), n_v, int(p["n_f"]), ld,
+                             t.data_ptr() if t is not None else None,
+                             c.data_ptr() if c is not None else None, cnt.data_ptr())
+        outs.append((t, c, cnt))
+    o = make_opts(path, gamma)
+    st = lib().ccc_2way_many(arr, len(problems), ctypes.byref(o), _stream(stream))
+    _raise(st, "ccc_2way_many")
+    return outs

@@ -1,0 +1,254 @@
+// api.hip -- the C ABI declared in include/ccc.h: argument validation, the
+// per-device workspace, and dispatch to the kernels.
+//
+// Validation is pure host logic and runs before any HIP call, so every error
+// path returns with nothing enqueued and outputs untouched.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/ccc.h"
+#include "kernels.h"
+#include "many.h"
+
+namespace {
+
+constexpr int64_t kInt32Max = 2147483647;
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+std::mutex g_mu;
+std::vector<Workspace> g_ws;  // indexed by device ordinal
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int resolve_opts(const ccc_opts* opts, ccc_opts* out) {
+  *out = ccc_default_opts();
+  if (!opts) return CCC_OK;
+  if (opts->path < CCC_PATH_AUTO || opts->path > CCC_PATH_MFMA) return CCC_ERR_ARG;
+  if (!isfinite(opts->gamma)) return CCC_ERR_ARG;
+  if (opts->flags & ~(unsigned)(CCC_ACCUMULATE | CCC_FINALIZE)) return CCC_ERR_ARG;
+  *out = *opts;
+  return CCC_OK;
+}
+
+int check_input(const uint8_t* v, int64_t n, int64_t n_f, int64_t ld) {
+  if (n < 0 || n_f < 0 || ld < 0) return CCC_ERR_ARG;
+  if (n > kInt32Max) return CCC_ERR_ARG;
+  if (ld % 16 != 0) return CCC_ERR_ALIGN;
+  if (ld < (n_f + 3) / 4) return CCC_ERR_ARG;
+  if (n > 0 && !v) return CCC_ERR_ARG;
+  if (v && !aligned16(v)) return CCC_ERR_ALIGN;
+  return CCC_OK;
+}
+
+}  // namespace
+
+namespace ccc {
+
+// Workspace of at least `bytes` on the current device (grown on demand).
+int workspace(size_t bytes, void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CCC_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+  Workspace& w = g_ws[dev];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      // the old buffer may still be in use by enqueued work
+      if (hipDeviceSynchronize() != hipSuccess) return CCC_ERR_HIP;
+      (void)hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    if (hipMalloc(&w.ptr, want) != hipSuccess) {
+      (void)hipGetLastError();
+      return CCC_ERR_NOMEM;
+    }
+    w.bytes = want;
+  }
+  *out = w.ptr;
+  return CCC_OK;
+}
+
+static int run_pair2(const Pair2Args& a, int path, hipStream_t stream) {
+  hipError_t e = path == CCC_PATH_POPCOUNT ? launch_pop2(a, stream) : launch_mfma2(a, stream);
+  return e == hipSuccess ? CCC_OK : CCC_ERR_HIP;
+}
+
+}  // namespace ccc
+
+extern "C" {
+
+ccc_opts ccc_default_opts(void) {
+  ccc_opts o;
+  o.path = CCC_PATH_AUTO;
+  o.gamma = 2.0 / 3.0;
+  o.flags = 0;
+  return o;
+}
+
+int ccc_version(void) { return 100; }
+
+const char* ccc_status_string(int status) {
+  switch (status) {
+    case CCC_OK: return "ok";
+    case CCC_ERR_ARG: return "invalid argument";
+    case CCC_ERR_RANGE: return "a table entry could exceed the int32 range";
+    case CCC_ERR_ALIGN: return "pointer not 16-byte aligned or row stride not a multiple of 16";
+    case CCC_ERR_HIP: return "HIP call or kernel launch failed";
+    case CCC_ERR_NOMEM: return "workspace allocation failed";
+    case CCC_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int ccc_2way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+  ccc_opts o;
+  int st = resolve_opts(opts, &o);
+  if (st) return st;
+  if (o.flags != 0) return CCC_ERR_ARG;
+  if ((st = check_input(v, n_v, n_f, ld))) return st;
+  if (4 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  if (n_v >= 2 && !tables && !ccc) return CCC_ERR_ARG;
+  if (!aligned16(tables) || !aligned16(ccc) || !aligned16(counts)) return CCC_ERR_ALIGN;
+  if (n_v == 0) return CCC_OK;
+  if (n_v == 1) {
+    if (!counts) return CCC_OK;
+    return ccc::launch_count1(v, ld, n_v, n_f, counts, 0, stream) == hipSuccess ? CCC_OK
+                                                                                  : CCC_ERR_HIP;
+  }
+  int32_t* cnt = counts;
+  if (!cnt) {
+    void* ws = nullptr;
+    if ((st = ccc::workspace((size_t)n_v * 16, &ws))) return st;
+    cnt = static_cast<int32_t*>(ws);
+  }
+  if (ccc::launch_count1(v, ld, n_v, n_f, cnt, 0, stream) != hipSuccess) return CCC_ERR_HIP;
+  ccc::Pair2Args a{};
+  a.va = v; a.lda = ld; a.n_a = n_v;
+  a.vb = v; a.ldb = ld; a.n_b = n_v;
+  a.n_f = n_f;
+  a.tri = 1;
+  a.accumulate = 0;
+  a.tables = tables;
+  a.ccc = ccc;
+  a.counts_a = cnt;
+  a.counts_b = cnt;
+  a.gamma = o.gamma;
+  return ccc::run_pair2(a, o.path, stream);
+}
+
+int ccc_3way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+  ccc_opts o;
+  int st = resolve_opts(opts, &o);
+  if (st) return st;
+  if (o.flags != 0) return CCC_ERR_ARG;
+  if ((st = check_input(v, n_v, n_f, ld))) return st;
+  if (8 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  if (n_v >= 3 && !tables && !ccc) return CCC_ERR_ARG;
+  if (!aligned16(tables) || !aligned16(ccc) || !aligned16(counts)) return CCC_ERR_ALIGN;
+  if (n_v > 2642245) return CCC_ERR_ARG;  // C(n_v,3) * 8 must fit int64 indexing
+  if (n_v == 0) return CCC_OK;
+  if (n_v < 3) {
+    if (!counts) return CCC_OK;
+    return ccc::launch_count1(v, ld, n_v, n_f, counts, 0, stream) == hipSuccess ? CCC_OK
+                                                                                  : CCC_ERR_HIP;
+  }
+  // workspace: offsets of the tetrahedral work units, then (if needed) counts
+  const size_t offs_bytes = ((size_t)(n_v + 1) * 8 + 255) / 256 * 256;
+  void* ws = nullptr;
+  if ((st = ccc::workspace(offs_bytes + (counts ? 0 : (size_t)n_v * 16), &ws))) return st;
+  int32_t* cnt = counts ? counts : reinterpret_cast<int32_t*>(static_cast<char*>(ws) + offs_bytes);
+  if (ccc::launch_count1(v, ld, n_v, n_f, cnt, 0, stream) != hipSuccess) return CCC_ERR_HIP;
+  ccc::Triple3Args a{};
+  a.v = v; a.ld = ld; a.n = n_v; a.n_f = n_f;
+  a.tables = tables;
+  a.ccc = ccc;
+  a.counts = cnt;
+  a.gamma = o.gamma;
+  a.offs = static_cast<int64_t*>(ws);
+  hipError_t e = o.path == CCC_PATH_POPCOUNT ? ccc::launch_pop3(a, stream)
+                                             : ccc::launch_mfma3(a, stream);
+  return e == hipSuccess ? CCC_OK : CCC_ERR_HIP;
+}
+
+int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* vb, int64_t n_b,
+                   int64_t ldb, int64_t n_f, int32_t* tables, int32_t* counts_a,
+                   int32_t* counts_b, double* ccc, const ccc_opts* opts, hipStream_t stream) {
+  ccc_opts o;
+  int st = resolve_opts(opts, &o);
+  if (st) return st;
+  if ((st = check_input(va, n_a, n_f, lda))) return st;
+  if ((st = check_input(vb, n_b, n_f, ldb))) return st;
+  if (4 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  const bool acc = (o.flags & CCC_ACCUMULATE) != 0, fin = (o.flags & CCC_FINALIZE) != 0;
+  if (n_a > 0 && n_b > 0) {
+    if (!tables || !counts_a || !counts_b) return CCC_ERR_ARG;
+    if (fin && !ccc) return CCC_ERR_ARG;
+  }
+  if (!aligned16(tables) || !aligned16(ccc) || !aligned16(counts_a) || !aligned16(counts_b))
+    return CCC_ERR_ALIGN;
+  if (n_a == 0 || n_b == 0) return CCC_OK;
+  if (ccc::launch_count1(va, lda, n_a, n_f, counts_a, acc, stream) != hipSuccess)
+    return CCC_ERR_HIP;
+  if (ccc::launch_count1(vb, ldb, n_b, n_f, counts_b, acc, stream) != hipSuccess)
+    return CCC_ERR_HIP;
+  ccc::Pair2Args a{};
+  a.va = va; a.lda = lda; a.n_a = n_a;
+  a.vb = vb; a.ldb = ldb; a.n_b = n_b;
+  a.n_f = n_f;
+  a.tri = 0;
+  a.accumulate = acc ? 1 : 0;
+  a.tables = tables;
+  a.ccc = fin ? ccc : nullptr;
+  a.counts_a = counts_a;
+  a.counts_b = counts_b;
+  a.gamma = o.gamma;
+  return ccc::run_pair2(a, o.path, stream);
+}
+
+int ccc_2way_many(const ccc_problem* probs, int n_probs, const ccc_opts* opts,
+                  hipStream_t stream) {
+  ccc_opts o;
+  int st = resolve_opts(opts, &o);
+  if (st) return st;
+  if (o.flags != 0) return CCC_ERR_ARG;
+  if (n_probs < 0 || (n_probs > 0 && !probs)) return CCC_ERR_ARG;
+  for (int p = 0; p < n_probs; ++p) {
+    const ccc_problem& q = probs[p];
+    if ((st = check_input(q.v, q.n_v, q.n_f, q.ld))) return st;
+    if (4 * q.n_f > kInt32Max) return CCC_ERR_RANGE;
+    if (q.n_v >= 2 && !q.tables && !q.ccc) return CCC_ERR_ARG;
+    if (!aligned16(q.tables) || !aligned16(q.ccc) || !aligned16(q.counts)) return CCC_ERR_ALIGN;
+  }
+  if (n_probs == 0) return CCC_OK;
+  return ccc::run_many(probs, n_probs, o, stream);
+}
+
+void ccc_release_workspace(void) {
+  ccc::release_many_cache();
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (size_t d = 0; d < g_ws.size(); ++d) {
+    if (!g_ws[d].ptr) continue;
+    if (hipSetDevice((int)d) == hipSuccess) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(g_ws[d].ptr);
+    }
+    g_ws[d] = Workspace{};
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// kernels.h -- host-side launchers of the CCC kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccc {
+
+// Arguments of one 2-way tally launch: either the upper triangle (i < j) of
+// one vector set (tri = 1, va == vb) or the full rectangle A x B (tri = 0).
+struct Pair2Args {
+  const uint8_t* va;
+  int64_t lda, n_a;
+  const uint8_t* vb;
+  int64_t ldb, n_b;
+  int64_t n_f;
+  int tri;
+  int accumulate;             // tables += result (rectangle only)
+  int32_t* tables;            // may be null when ccc is set
+  double* ccc;                // may be null
+  const int32_t* counts_a;    // [n_a][4]
+  const int32_t* counts_b;    // [n_b][4]
+  double gamma;
+};
+
+// Arguments of one 3-way tally launch over all triples i < j < k.
+struct Triple3Args {
+  const uint8_t* v;
+  int64_t ld, n, n_f;
+  int32_t* tables;
+  double* ccc;
+  const int32_t* counts;
+  double gamma;
+  int64_t* offs;  // workspace: n+1 int64 (work-unit offsets per middle vector)
+};
+
+enum Path { kPathPopcount = 1, kPathMfma = 2 };
+
+hipError_t launch_count1(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int32_t* counts,
+                         int accumulate, hipStream_t stream);
+hipError_t launch_pop2(const Pair2Args& a, hipStream_t stream);
+hipError_t launch_mfma2(const Pair2Args& a, hipStream_t stream);
+hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream);
+hipError_t launch_pop3(const Triple3Args& a, hipStream_t stream);
+
+}  // namespace ccc

@@ -1,0 +1,119 @@
+"""The C ABI of libccc.so without a GPU: symbols, status codes and every
+argument-validation path (validation runs before any HIP call, so these calls
+enqueue nothing and touch no memory)."""
+import ctypes
+
+import pytest
+
+import paper_1705_08213_amd as ccc
+
+FAKE = 0x10000  # 16-byte aligned, never dereferenced by a failing call
+I32MAX = 2**31 - 1
+
+
+def test_library_exports_every_declared_function():
+    L = ccc.lib()
+    names = ccc.header_functions()
+    assert {"ccc_2way", "ccc_3way", "ccc_2way_block", "ccc_2way_many",
+            "ccc_status_string"} <= set(names)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version():
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        s = ccc.status_string(st)
+        assert s and s != "unknown status"
+    assert ccc.status_string(-99) == "unknown status"
+    assert ccc.version() >= 100
+
+
+def test_default_opts():
+    o = ccc.lib().ccc_default_opts()
+    assert o.path == ccc.CCC_PATH_AUTO and o.flags == 0
+    assert o.gamma == 2.0 / 3.0
+
+
+def call2(v=FAKE, n_v=10, n_f=100, ld=32, tables=FAKE, cc=FAKE, counts=None, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return ccc.lib().ccc_2way(v, n_v, n_f, ld, tables, cc, counts, o, None)
+
+
+def call3(v=FAKE, n_v=10, n_f=100, ld=32, tables=FAKE, cc=FAKE, counts=None, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return ccc.lib().ccc_3way(v, n_v, n_f, ld, tables, cc, counts, o, None)
+
+
+def callb(va=FAKE, n_a=8, lda=32, vb=FAKE, n_b=9, ldb=32, n_f=100, tables=FAKE, ca=FAKE,
+          cb=FAKE, cc=FAKE, flags=ccc.CCC_FINALIZE, path=0):
+    o = ccc.make_opts(path, flags=flags)
+    return ccc.lib().ccc_2way_block(va, n_a, lda, vb, n_b, ldb, n_f, tables, ca, cb, cc,
+                                    ctypes.byref(o), None)
+
+
+@pytest.mark.parametrize("fn", [call2, call3])
+def test_validation_errors_common(fn):
+    assert fn(v=None) == ccc.CCC_ERR_ARG
+    assert fn(n_v=-1) == ccc.CCC_ERR_ARG
+    assert fn(n_f=-5) == ccc.CCC_ERR_ARG
+    assert fn(ld=-16) == ccc.CCC_ERR_ARG
+    assert fn(ld=24) == ccc.CCC_ERR_ALIGN            # ld % 16 != 0
+    assert fn(ld=16) == ccc.CCC_ERR_ARG              # ld < ceil(100/4)
+    assert fn(v=FAKE + 4) == ccc.CCC_ERR_ALIGN
+    assert fn(tables=FAKE + 8) == ccc.CCC_ERR_ALIGN
+    assert fn(cc=FAKE + 8) == ccc.CCC_ERR_ALIGN
+    assert fn(counts=FAKE + 4) == ccc.CCC_ERR_ALIGN
+    assert fn(tables=None, cc=None) == ccc.CCC_ERR_ARG
+    assert fn(opts=ccc.make_opts(3)) == ccc.CCC_ERR_ARG
+    assert fn(opts=ccc.make_opts(0, float("nan"))) == ccc.CCC_ERR_ARG
+    assert fn(opts=ccc.make_opts(0, flags=ccc.CCC_ACCUMULATE)) == ccc.CCC_ERR_ARG
+    assert fn(opts=ccc.make_opts(0, flags=64)) == ccc.CCC_ERR_ARG
+
+
+def test_range_limits():
+    big = I32MAX // 4 + 1  # 4 * n_f exceeds INT32_MAX
+    assert call2(n_f=big, ld=(big + 3) // 4 // 16 * 16 + 16) == ccc.CCC_ERR_RANGE
+    ok_2way_but_not_3way = I32MAX // 8 + 1
+    ld = (ok_2way_but_not_3way + 3) // 4 // 16 * 16 + 16
+    assert call3(n_f=ok_2way_but_not_3way, ld=ld) == ccc.CCC_ERR_RANGE
+    assert callb(n_f=big, lda=(big + 3) // 4 // 16 * 16 + 16,
+                 ldb=(big + 3) // 4 // 16 * 16 + 16) == ccc.CCC_ERR_RANGE
+
+
+def test_empty_problems_return_ok_without_work():
+    assert call2(v=None, n_v=0, tables=None, cc=None) == ccc.CCC_OK
+    assert call2(n_v=1, tables=None, cc=None, counts=None) == ccc.CCC_OK
+    assert call3(v=None, n_v=0) == ccc.CCC_OK
+    assert call3(n_v=2, tables=None, cc=None) == ccc.CCC_OK
+    assert callb(n_a=0, va=None, tables=None, ca=None, cb=None, cc=None) == ccc.CCC_OK
+    assert callb(n_b=0, vb=None, tables=None, ca=None, cb=None, cc=None) == ccc.CCC_OK
+    assert ccc.lib().ccc_2way_many(None, 0, None, None) == ccc.CCC_OK
+
+
+def test_block_validation():
+    assert callb(tables=None) == ccc.CCC_ERR_ARG
+    assert callb(ca=None) == ccc.CCC_ERR_ARG
+    assert callb(cb=None) == ccc.CCC_ERR_ARG
+    assert callb(cc=None) == ccc.CCC_ERR_ARG                    # FINALIZE needs ccc
+    assert callb(lda=24) == ccc.CCC_ERR_ALIGN
+    assert callb(ldb=16) == ccc.CCC_ERR_ARG
+    assert callb(vb=FAKE + 1) == ccc.CCC_ERR_ALIGN
+    assert callb(ca=FAKE + 4) == ccc.CCC_ERR_ALIGN
+    assert callb(flags=8) == ccc.CCC_ERR_ARG
+    assert callb(path=7) == ccc.CCC_ERR_ARG
+
+
+def test_many_validation_checks_every_problem():
+    P = ccc.ccc_problem
+    good = P(FAKE, 10, 100, 32, FAKE, FAKE, FAKE)
+    bad_ld = P(FAKE, 10, 100, 24, FAKE, FAKE, FAKE)
+    bad_out = P(FAKE, 10, 100, 32, None, None, FAKE)
+    big = I32MAX // 4 + 1
+    bad_range = P(FAKE, 10, big, (big + 3) // 4 // 16 * 16 + 16, FAKE, FAKE, FAKE)
+    L = ccc.lib()
+    for bad, want in [(bad_ld, ccc.CCC_ERR_ALIGN), (bad_out, ccc.CCC_ERR_ARG),
+                      (bad_range, ccc.CCC_ERR_RANGE)]:
+        arr = (P * 3)(good, good, bad)
+        assert L.ccc_2way_many(arr, 3, None, None) == want
+    assert L.ccc_2way_many(None, 2, None, None) == ccc.CCC_ERR_ARG
+    assert L.ccc_2way_many(None, -1, None, None) == ccc.CCC_ERR_ARG
