@@ -168,6 +168,18 @@ const char* ccc_status_string(int status);
 /* Free the workspace and cached graphs of every device (waits for the device). */
 void ccc_release_workspace(void);
 
+/*
+ * Kernel timing (profiling aid, off by default).  While enabled, the library
+ * records a pair of HIP events on the launching stream around each tally
+ * kernel launch; names are "count1", "pop2", "mfma2", "pop3", "mfma3".
+ * Do not enable it while a stream is being captured into a graph.
+ *   ccc_timing_query: total milliseconds and number of recorded launches of
+ *   kernel `name` (NULL = all); waits for the recorded events.
+ */
+void ccc_timing_enable(int on);
+void ccc_timing_reset(void);
+double ccc_timing_query(const char* name, int* count);
+
 /* Library version: major*10000 + minor*100 + patch. */
 int ccc_version(void);
 

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libccc.so")
 
-SOURCES = ["api.hip", "count1.hip", "pop2.hip", "mfma2.hip", "pop3.hip", "mfma3.hip", "many.hip"]
+SOURCES = ["api.hip", "count1.hip", "pop2.hip", "mfma2.hip", "pop3.hip", "mfma3.hip", "many.hip",
+           "timing.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -160,6 +160,10 @@ __device__ __forceinline__ void unit_coords(int64_t u, int64_t n, int64_t bi, in
 }  // namespace ccc
 
 namespace ccc {
+
+void timing_begin(const char* name, hipStream_t stream);
+void timing_end(hipStream_t stream);
+
 namespace {
 
 // offs[j] = number of units of all j' < j, for j = 0..n (one workgroup).
@@ -192,7 +196,7 @@ __global__ void unit_offsets_kernel(int64_t n, int64_t bi, int64_t bk,
 // Launch a 3-way kernel over all its tetrahedral units (256 threads each),
 // in slices of at most 2^30 workgroups.  a.offs must hold n+1 int64.
 template <typename Kernel, typename Args>
-hipError_t launch_units(Kernel kernel, const Args& a, int64_t bi, int64_t bk,
+hipError_t launch_units(Kernel kernel, const Args& a, int64_t bi, int64_t bk, const char* name,
                         hipStream_t stream) {
   int64_t total = 0;
   for (int64_t j = 0; j < a.n; ++j) total += units_for_j(j, a.n, bi, bk);
@@ -201,13 +205,15 @@ hipError_t launch_units(Kernel kernel, const Args& a, int64_t bi, int64_t bk,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t kMaxGrid = 0x40000000;
+  timing_begin(name, stream);
   for (int64_t base = 0; base < total; base += kMaxGrid) {
     int64_t cnt = total - base < kMaxGrid ? total - base : kMaxGrid;
     hipLaunchKernelGGL(kernel, dim3((unsigned)cnt), dim3(256), 0, stream, a,
                        (const int64_t*)a.offs, base);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) break;
   }
-  return hipSuccess;
+  timing_end(stream);
+  return e;
 }
 
 }  // namespace

@@ -60,8 +60,10 @@ hipError_t launch_count1(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, i
                          int accumulate, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   dim3 grid((unsigned)((n + 3) / 4));
+  timing_begin("count1", stream);
   hipLaunchKernelGGL(count1_kernel, grid, dim3(256), 0, stream, v, ld, n, n_f, counts,
                      accumulate);
+  timing_end(stream);
   return hipGetLastError();
 }
 

@@ -36,6 +36,11 @@ struct Triple3Args {
 
 enum Path { kPathPopcount = 1, kPathMfma = 2 };
 
+// Optional event timing around the main kernel of a launcher (no-ops unless
+// enabled through ccc_timing_enable).
+void timing_begin(const char* name, hipStream_t stream);
+void timing_end(hipStream_t stream);
+
 hipError_t launch_count1(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int32_t* counts,
                          int accumulate, hipStream_t stream);
 hipError_t launch_pop2(const Pair2Args& a, hipStream_t stream);

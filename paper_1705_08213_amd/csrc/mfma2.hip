@@ -179,8 +179,10 @@ hipError_t launch_shape(const Pair2Args& a, hipStream_t stream) {
   int64_t ntiles = a.tri ? tm * (tm + 1) : tm * tn;  // triangle: two halves per square
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  timing_begin("mfma2", stream);
   hipLaunchKernelGGL((mfma2_kernel<WM, WN>), dim3((unsigned)ntiles), dim3(256), 0, stream, a, tm,
                      tn);
+  timing_end(stream);
   return hipGetLastError();
 }
 

@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a,
 }  // namespace
 
 hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream) {
-  return launch_units(mfma3_kernel, a, BI, BK, stream);
+  return launch_units(mfma3_kernel, a, BI, BK, "mfma3", stream);
 }
 
 }  // namespace ccc

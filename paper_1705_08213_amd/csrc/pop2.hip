@@ -148,7 +148,9 @@ hipError_t launch_pop2(const Pair2Args& a, hipStream_t stream) {
   int64_t ntiles = a.tri ? tm * (tm + 1) / 2 : tm * tn;
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  timing_begin("pop2", stream);
   hipLaunchKernelGGL(pop2_kernel, dim3((unsigned)ntiles), dim3(256), 0, stream, a, tm, tn);
+  timing_end(stream);
   return hipGetLastError();
 }
 

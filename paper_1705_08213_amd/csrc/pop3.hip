@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
 }  // namespace
 
 hipError_t launch_pop3(const Triple3Args& a, hipStream_t stream) {
-  return launch_units(pop3_kernel, a, kTile, kTile, stream);
+  return launch_units(pop3_kernel, a, kTile, kTile, "pop3", stream);
 }
 
 }  // namespace ccc
