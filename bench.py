@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Throughput of the CCC tally hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+
+A step is one call of the library's entry point for the workload (1-way
+count pass, tally kernel and fused FP64 epilogue writing every table and CCC
+value) on inputs already resident in HBM.  The default workload is the large
+2-way configuration (n_v = 32768 vectors x n_f = 65536 fields, per-vector
+allele frequency ~ Beta(1/2,1/2), Hardy-Weinberg genotypes, 1% missing) on
+the int8-MFMA path; the popcount path is timed on the same input for the
+ratio.  Prints one JSON line.
+
+Other workloads (--config): c1 (2-way 512 x 1000, popcount path), c3 (3-way
+2048 x 16384), c4 (64 batched 2-way problems), c5 (2-way off-diagonal block
+16384 x 16384 over 131072 fields in 8 chunks).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def timing_query(lib, name):
+    cnt = ctypes.c_int(0)
+    lib.ccc_timing_query.restype = ctypes.c_double
+    lib.ccc_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
+    ms = lib.ccc_timing_query(name.encode(), ctypes.byref(cnt))
+    return ms, cnt.value
+
+
+def timed(fn, steps, warmup, lib, kernel):
+    """Run fn warmup+steps times; returns (ms per step, mean kernel ms, launches)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    lib.ccc_timing_reset()
+    lib.ccc_timing_enable(1)
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    lib.ccc_timing_enable(0)
+    total = e0.elapsed_time(e1)
+    kms, kn = timing_query(lib, kernel)
+    lib.ccc_timing_reset()
+    return total / steps, (kms / kn if kn else None), kn
+
+
+def cpu_baseline_2way(v, n_f, rows):
+    """The oracle on rows [0, rows) x all later vectors (plain loops, OpenMP)."""
+    import oracle
+    n_v = v.shape[0]
+    t = time.perf_counter()
+    oracle.two_way(v, n_f, 0, rows, with_ccc=True)
+    dt = time.perf_counter() - t
+    pairs = sum(n_v - 1 - i for i in range(rows))
+    return dict(value=pairs * n_f / dt, unit="comparisons/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"rows i in [0,{rows}) x all j>i of the same input ({pairs} pairs x "
+                       f"{n_f} fields, {dt:.1f} s)")
+
+
+def cpu_baseline_3way(v, n_f, rows):
+    import oracle
+    n_v = v.shape[0]
+    t = time.perf_counter()
+    oracle.three_way(v, n_f, 0, rows, with_ccc=True)
+    dt = time.perf_counter() - t
+    tri = sum((n_v - 1 - i) * (n_v - 2 - i) // 2 for i in range(rows))
+    return dict(value=tri * n_f / dt, unit="comparisons/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"triples with i in [0,{rows}) of the same input ({tri} triples x "
+                       f"{n_f} fields, {dt:.1f} s)")
+
+
+def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
+    import torch
+    import paper_1705_08213_amd as ccc
+    import synth
+    log(f"generating {n_v} x {n_f} input")
+    v = (synth.beta_hw if gen == "beta_hw" else synth.uniform)(n_v, n_f, seed=0,
+                                                                missing=missing)
+    dv = torch.from_numpy(v).cuda()
+    P = ccc.n_pairs(n_v)
+    tables = torch.empty((P, 4), dtype=torch.int32, device="cuda")
+    cc = torch.empty((P, 4), dtype=torch.float64, device="cuda")
+    counts = torch.empty((n_v, 4), dtype=torch.int32, device="cuda")
+    kernel = "mfma2" if path == "mfma" else "pop2"
+
+    def step(p=path):
+        ccc.ccc_2way(dv, n_f, tables, cc, counts, path=p)
+
+    log(f"timing {path}: {args.warmup} warmup + {args.steps} steps")
+    ms, kms, _ = timed(step, args.steps, args.warmup, lib, kernel)
+    comps = P * n_f
+    rate = comps / (ms / 1e3)
+    out = dict(metric="CCC comparisons/sec (pairs*n_f), bit-exact tables", value=rate,
+               unit="comparisons/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="i8" if path == "mfma" else "u32", data="synthetic",
+               config=dict(workload=workload, n_v=n_v, n_f=n_f, missing=missing, path=path))
+    if path == "mfma":
+        ops = 8.0 * comps  # 4 int8 MACs per comparison
+        ach = ops / (kms / 1e3) / 1e12
+        out["roofline"] = dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
+                               frac=ach / INT8_PEAK_TOPS, traffic=None,
+                               kernel="mfma2_kernel", kernel_ms=kms)
+        if args.pop_steps > 0:
+            log(f"timing popcount: 1 warmup + {args.pop_steps} steps")
+            pms, pkms, _ = timed(lambda: step("popcount"), args.pop_steps, 1, lib, "pop2")
+            prate = comps / (pms / 1e3)
+            out["popcount"] = dict(value=prate, ms_per_step=pms, kernel_ms=pkms)
+            out["mfma_over_popcount"] = rate / prate
+    else:
+        out["roofline"] = dict(bound="alu", achieved=None, peak=None, unit=None, frac=None,
+                               traffic=None, kernel="pop2_kernel", kernel_ms=kms)
+    if not args.no_cpu:
+        log(f"timing the CPU oracle on {cpu_rows} rows")
+        out["cpu_baseline"] = cpu_baseline_2way(v, n_f, cpu_rows)
+    return out
+
+
+def bench_3way(args, lib):
+    import torch
+    import paper_1705_08213_amd as ccc
+    import synth
+    n_v, n_f, missing = 2048, 16384, 0.005
+    log(f"generating {n_v} x {n_f} input")
+    v = synth.beta_hw(n_v, n_f, seed=0, missing=missing)
+    dv = torch.from_numpy(v).cuda()
+    T = ccc.n_triples(n_v)
+    tables = torch.empty((T, 8), dtype=torch.int32, device="cuda")
+    cc = torch.empty((T, 8), dtype=torch.float64, device="cuda")
+    counts = torch.empty((n_v, 4), dtype=torch.int32, device="cuda")
+
+    def step():
+        ccc.ccc_3way(dv, n_f, tables, cc, counts, path="mfma")
+
+    ms, kms, _ = timed(step, args.steps, args.warmup, lib, "mfma3")
+    comps = T * n_f
+    ach = 16.0 * comps / (kms / 1e3) / 1e12
+    out = dict(metric="CCC comparisons/sec (triples*n_f), bit-exact tables",
+               value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="i8", data="synthetic",
+               config=dict(workload="3-way CCC: n_v=2048 x n_f=16384, Beta/HW, 0.5% missing",
+                           n_v=n_v, n_f=n_f, missing=missing, path="mfma"),
+               roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
+                             frac=ach / INT8_PEAK_TOPS, traffic=None, kernel="mfma3_kernel",
+                             kernel_ms=kms))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_3way(v, n_f, 1)
+    return out
+
+
+def bench_block(args, lib):
+    import torch
+    import paper_1705_08213_amd as ccc
+    import synth
+    n, n_f, chunk, missing = 16384, 131072, 16384, 0.02
+    log(f"generating 2 x {n} x {n_f} input")
+    va = torch.from_numpy(synth.beta_hw(n, n_f, seed=0, missing=missing)).cuda()
+    vb = torch.from_numpy(synth.beta_hw(n, n_f, seed=1, missing=missing)).cuda()
+    tables = torch.empty((n, n, 4), dtype=torch.int32, device="cuda")
+    cc = torch.empty((n, n, 4), dtype=torch.float64, device="cuda")
+    ca = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    cb = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    nchunks = n_f // chunk
+
+    def step():
+        for k in range(nchunks):
+            ccc.ccc_2way_block(va, vb, chunk, tables, ca, cb, cc, accumulate=k > 0,
+                               finalize=k == nchunks - 1, field_offset=k * chunk // 4)
+
+    ms, kms, kn = timed(step, args.steps, args.warmup, lib, "mfma2")
+    comps = n * n * n_f
+    per_launch = 8.0 * n * n * chunk
+    ach = per_launch / (kms / 1e3) / 1e12
+    return dict(metric="CCC comparisons/sec (n_a*n_b*n_f), bit-exact tables",
+                value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="i8", data="synthetic",
+                config=dict(workload="2-way block 16384 x 16384, n_f=131072 in 8 chunks of "
+                                     "16384, Beta/HW, 2% missing", path="mfma"),
+                roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
+                              frac=ach / INT8_PEAK_TOPS, traffic=None, kernel="mfma2_kernel",
+                              kernel_ms=kms))
+
+
+def bench_many(args, lib):
+    import torch
+    import paper_1705_08213_amd as ccc
+    import synth
+    nv, nf = synth.batch_sizes(64, seed=0)
+    log(f"generating 64 problems, sum n_v = {int(nv.sum())}")
+    probs = []
+    comps = 0
+    for k in range(64):
+        v = synth.beta_hw(int(nv[k]), int(nf[k]), seed=100 + k, missing=0.01)
+        probs.append(dict(v=torch.from_numpy(v).cuda(), n_f=int(nf[k])))
+        comps += ccc.n_pairs(int(nv[k])) * int(nf[k])
+    outs = ccc.ccc_2way_many(probs)
+    for p, (t, c, cnt) in zip(probs, outs):
+        p.update(tables=t, ccc=c, counts=cnt)
+
+    def step():
+        ccc.ccc_2way_many(probs)
+
+    ms, kms, kn = timed(step, args.steps, args.warmup, lib, "mfma2")
+    return dict(metric="CCC comparisons/sec (sum pairs*n_f), bit-exact tables",
+                value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="i8", data="synthetic",
+                config=dict(workload="64 batched 2-way problems, n_v log-uniform [256,8192], "
+                                     "n_f uniform [1000,50000], Beta/HW, 1% missing",
+                            path="mfma"),
+                roofline=dict(bound="mfma", achieved=8.0 * comps / (ms / 1e3) / 1e12,
+                              peak=INT8_PEAK_TOPS, unit="TFLOP/s",
+                              frac=8.0 * comps / (ms / 1e3) / 1e12 / INT8_PEAK_TOPS,
+                              traffic=None, kernel="whole step"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pop-steps", type=int, default=2, help="popcount-path steps (c2)")
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps(dict(error="this benchmark runs on exactly one GPU; multi-GPU "
+                                    "sharding is not part of this build", n_gpus=args.gpus)))
+        sys.exit(2)
+    import torch
+    import paper_1705_08213_amd as ccc
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    lib = ccc.lib()
+    lib.ccc_timing_enable.argtypes = [ctypes.c_int]
+    if args.config == "c2":
+        out = bench_2way(args, lib, 32768, 65536, 0.01, "beta_hw", "mfma",
+                         "2-way CCC large: n_v=32768 x n_f=65536, Beta(0.5,0.5)/Hardy-Weinberg, "
+                         "1% missing", args.cpu_rows)
+    elif args.config == "c1":
+        out = bench_2way(args, lib, 512, 1000, 0.0, "uniform", "popcount",
+                         "2-way CCC: n_v=512 x n_f=1000, uniform genotypes, no missing", 512)
+    elif args.config == "c3":
+        out = bench_3way(args, lib)
+    elif args.config == "c4":
+        out = bench_many(args, lib)
+    else:
+        out = bench_block(args, lib)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
