@@ -35,6 +35,27 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def committed_traffic(kernel_sources, profile):
+    """HBM bytes per launch recorded in a committed rocprofv3 summary, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                    for f in kernel_sources)).hexdigest()[:16]
+        text = open(os.path.join(ROOT, profile)).read()
+    except OSError:
+        return None
+    m1 = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    m2 = re.search(r"kernel_source_sha256_16: ([0-9a-f]+)", text)
+    if m1 and m2 and m2.group(1) == h:
+        return int(m1.group(1))
+    return None
+
+
+MFMA2_SOURCES = ["paper_1705_08213_amd/csrc/mfma2.hip", "paper_1705_08213_amd/csrc/common.h"]
+
+
 def timing_query(lib, name):
     cnt = ctypes.c_int(0)
     lib.ccc_timing_query.restype = ctypes.c_double
@@ -123,8 +144,14 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
     if path == "mfma":
         ops = 8.0 * comps  # 4 int8 MACs per comparison
         ach = ops / (kms / 1e3) / 1e12
+        traffic = None
+        if (n_v, n_f) == (32768, 65536):
+            traffic = committed_traffic(MFMA2_SOURCES,
+                                        "profiles/mfma2_2way_n32768_f65536_traffic.md")
         out["roofline"] = dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                               frac=ach / INT8_PEAK_TOPS, traffic=None,
+                               frac=ach / INT8_PEAK_TOPS, traffic=traffic,
+                               traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
+                               algorithmic_bytes=n_v * ((n_f + 3) // 4) + 48 * P + 32 * n_v,
                                kernel="mfma2_kernel", kernel_ms=kms)
         if args.pop_steps > 0:
             log(f"timing popcount: 1 warmup + {args.pop_steps} steps")
@@ -250,6 +277,9 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain elementwise copy of 1 GiB (read 1 GiB, write 1 GiB) "
+                         "to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps(dict(error="this benchmark runs on exactly one GPU; multi-GPU "
@@ -259,6 +289,15 @@ def main():
     import paper_1705_08213_amd as ccc
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(calibration="elementwise int32 add, 2^28 elements: reads 1 GiB, "
+                                          "writes 1 GiB per launch", launches=3)))
+        return
     lib = ccc.lib()
     lib.ccc_timing_enable.argtypes = [ctypes.c_int]
     if args.config == "c2":

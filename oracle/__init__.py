@@ -47,6 +47,9 @@ def _lib():
         lib.oracle_3way_rows.argtypes = [ptr, i64, i64, i64, i64, i64, ptr, dbl, ptr, ptr]
         lib.oracle_block_rows.argtypes = [ptr, i64, ptr, i64, i64, i64, i64, i64, ptr, ptr,
                                           dbl, ptr, ptr]
+        lib.oracle_2way_list.argtypes = [ptr, i64, ptr, i64, i64, ptr, ptr, i64, ptr, ptr, dbl,
+                                         ptr, ptr]
+        lib.oracle_3way_list.argtypes = [ptr, i64, i64, ptr, ptr, ptr, i64, ptr, dbl, ptr, ptr]
         lib.oracle_fp2_from_input.argtypes = [ptr, i64, i64, i64, ptr, ptr, ptr]
         lib.oracle_fp2_from_tables.argtypes = [ptr, i64, ptr, ptr, ptr]
         lib.oracle_fpb_from_input.argtypes = [ptr, i64, i64, ptr, i64, i64, i64, ptr, ptr, ptr]
@@ -156,6 +159,38 @@ def block(va, vb, n_f, a0=0, a1=None, gamma=GAMMA, with_ccc=True):
         _lib().oracle_block_rows(va.ctypes.data, lda, vb.ctypes.data, n_b, ldb, n_f, a0, a1,
                                  ca.ctypes.data, cb.ctypes.data, gamma, tables.ctypes.data,
                                  ccc.ctypes.data if with_ccc else None)
+    return tables, ccc
+
+
+def pairs_list(va, vb, n_f, ia, jb, gamma=GAMMA, counts_a=None, counts_b=None):
+    """Tables int64 [np, 4] and CCC [np, 4] for explicit pairs (ia[p] of A,
+    jb[p] of B); pass the same array as A and B for pairs of one set."""
+    va = _c(va, np.uint8)
+    vb = _c(vb, np.uint8)
+    ia = _c(ia, np.int64)
+    jb = _c(jb, np.int64)
+    ca = counts1(va, n_f) if counts_a is None else _c(counts_a, np.int64)
+    cb = (ca if vb is va else counts1(vb, n_f)) if counts_b is None else _c(counts_b, np.int64)
+    tables = np.zeros((len(ia), 4), dtype=np.int64)
+    ccc = np.zeros((len(ia), 4), dtype=np.float64)
+    if len(ia):
+        _lib().oracle_2way_list(va.ctypes.data, va.shape[1], vb.ctypes.data, vb.shape[1], n_f,
+                                ia.ctypes.data, jb.ctypes.data, len(ia), ca.ctypes.data,
+                                cb.ctypes.data, gamma, tables.ctypes.data, ccc.ctypes.data)
+    return tables, ccc
+
+
+def triples_list(v, n_f, ii, jj, kk, gamma=GAMMA, counts=None):
+    """Tables int64 [np, 8] and CCC [np, 8] for explicit triples."""
+    v = _c(v, np.uint8)
+    ii, jj, kk = (_c(x, np.int64) for x in (ii, jj, kk))
+    cnt = counts1(v, n_f) if counts is None else _c(counts, np.int64)
+    tables = np.zeros((len(ii), 8), dtype=np.int64)
+    ccc = np.zeros((len(ii), 8), dtype=np.float64)
+    if len(ii):
+        _lib().oracle_3way_list(v.ctypes.data, v.shape[1], n_f, ii.ctypes.data, jj.ctypes.data,
+                                kk.ctypes.data, len(ii), cnt.ctypes.data, gamma,
+                                tables.ctypes.data, ccc.ctypes.data)
     return tables, ccc
 
 

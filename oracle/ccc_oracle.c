@@ -251,6 +251,55 @@ void oracle_3way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, in
 }
 
 /* ------------------------------------------------------------------------- */
+/* Explicit lists of pairs / triples (sampled checks at full size).           */
+/* ------------------------------------------------------------------------- */
+
+/* 2-way tables and CCC for the pairs (ia[p] in A, jb[p] in B), p < np; for a
+   triangle pass the same set as A and B.  counts_a/counts_b are [n][3]. */
+void oracle_2way_list(const uint8_t* va, int64_t lda, const uint8_t* vb, int64_t ldb,
+                      int64_t n_f, const int64_t* ia, const int64_t* jb, int64_t np,
+                      const int64_t* counts_a, const int64_t* counts_b, double gamma,
+                      int64_t* tables, double* ccc) {
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t p = 0; p < np; ++p) {
+    const uint8_t* ri = va + ia[p] * lda;
+    const uint8_t* rj = vb + jb[p] * ldb;
+    int64_t t[4] = {0, 0, 0, 0};
+    for (int64_t q = 0; q < n_f; ++q) {
+      unsigned ci = code_at(ri, q), cj = code_at(rj, q);
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) t[2 * a + b] += (int64_t)rho(ci, a) * rho(cj, b);
+    }
+    for (int e = 0; e < 4; ++e) tables[p * 4 + e] = t[e];
+    if (ccc) ccc_pair(t, counts_a + ia[p] * 3, counts_b + jb[p] * 3, gamma, ccc + p * 4);
+  }
+}
+
+/* 3-way tables and CCC for the triples (ii[p], jj[p], kk[p]), p < np. */
+void oracle_3way_list(const uint8_t* v, int64_t ld, int64_t n_f, const int64_t* ii,
+                      const int64_t* jj, const int64_t* kk, int64_t np, const int64_t* counts,
+                      double gamma, int64_t* tables, double* ccc) {
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t p = 0; p < np; ++p) {
+    const uint8_t* ri = v + ii[p] * ld;
+    const uint8_t* rj = v + jj[p] * ld;
+    const uint8_t* rk = v + kk[p] * ld;
+    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t q = 0; q < n_f; ++q) {
+      unsigned ci = code_at(ri, q), cj = code_at(rj, q), ck = code_at(rk, q);
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          for (int c = 0; c < 2; ++c)
+            t[4 * a + 2 * b + c] += (int64_t)rho(ci, a) * rho(cj, b) * rho(ck, c);
+    }
+    for (int e = 0; e < 8; ++e) tables[p * 8 + e] = t[e];
+    if (ccc)
+      ccc_triple(t, counts + ii[p] * 3, counts + jj[p] * 3, counts + kk[p] * 3, gamma,
+                 ccc + p * 8);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Whole-output checksums mod 2^61 - 1.                                       */
 /* ------------------------------------------------------------------------- */
 

@@ -418,3 +418,26 @@ def test_fingerprints_match_direct_sums_and_detect_one_change():
     tb, _ = oracle.block(v, vb, n_f, with_ccc=False)
     fb = oracle.fpb_from_input(v, vb, n_f, w, u[:17])
     assert np.array_equal(fb, oracle.fpb_from_tables(tb.astype(np.int32), n_v, 17, w, u[:17]))
+
+
+def test_list_forms_match_the_row_forms():
+    n_v, n_f = 30, 901
+    v = synth.beta_hw(n_v, n_f, seed=18, missing=0.05)
+    t, c = oracle.two_way(v, n_f)
+    rng = np.random.default_rng(3)
+    ii = rng.integers(0, n_v - 1, 50)
+    jj = np.array([rng.integers(i + 1, n_v) for i in ii])
+    lt, lc = oracle.pairs_list(v, v, n_f, ii, jj)
+    idx = [oracle.pair_index(n_v, i, j) for i, j in zip(ii, jj)]
+    assert np.array_equal(lt, t[idx]) and np.array_equal(lc, c[idx])
+    t3, c3 = oracle.three_way(v, n_f)
+    tri = [tuple(sorted(rng.choice(n_v, 3, replace=False))) for _ in range(40)]
+    a, b, cc = (np.array(x) for x in zip(*tri))
+    lt3, lc3 = oracle.triples_list(v, n_f, a, b, cc)
+    idx3 = [oracle.triple_index(n_v, *x) for x in tri]
+    assert np.array_equal(lt3, t3[idx3]) and np.array_equal(lc3, c3[idx3])
+    vb = synth.beta_hw(11, n_f, seed=19, missing=0.05)
+    tb, cb = oracle.block(v, vb, n_f)
+    jb = rng.integers(0, 11, 50)
+    lbt, lbc = oracle.pairs_list(v, vb, n_f, ii, jb)
+    assert np.array_equal(lbt, tb[ii, jb]) and np.array_equal(lbc, cb[ii, jb])
