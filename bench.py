@@ -53,7 +53,8 @@ def committed_traffic(kernel_sources, profile):
     return None
 
 
-MFMA2_SOURCES = ["paper_1705_08213_amd/csrc/mfma2.hip", "paper_1705_08213_amd/csrc/common.h"]
+MFMA2_SOURCES = ["paper_1705_08213_amd/csrc/mfma2.hip", "paper_1705_08213_amd/csrc/tile2.h",
+                 "paper_1705_08213_amd/csrc/common.h"]
 
 
 def timing_query(lib, name):

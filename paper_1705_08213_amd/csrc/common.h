@@ -111,6 +111,52 @@ __device__ __forceinline__ void store_pair(int64_t p, v4i t, v4i ci, v4i cj, dou
 
 namespace ccc {
 
+// 1-way counts of one packed row by one wave (64 lanes): writes or adds
+// (n(0), n(1), m, 0) at out[0..3] from lane 0.  Popcounts on the bit planes:
+// b0 = low bits (01, 11), b1 = high bits (11, 10); n(1) = pop(b0) +
+// pop(b0 & b1), missing = pop(b1 & ~b0), n(0) = 2m - n(1).
+__device__ __forceinline__ void count_row_wave(const uint8_t* __restrict__ r, int64_t n_f,
+                                               int32_t* __restrict__ out, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nbytes = (n_f + 3) / 4;
+  int n1 = 0, miss = 0;
+  for (int64_t ob = (int64_t)lane * 16; ob < nbytes; ob += 64 * 16) {
+    u4 w = load_fields64(r, ob, n_f);
+    unsigned ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      unsigned b0 = ws[s] & kEven, b1 = (ws[s] >> 1) & kEven;
+      n1 += __popc(b0) + __popc(b0 & b1);
+      miss += __popc(b1 & ~b0);
+    }
+  }
+  // fields covered by the loop minus missing ones (masked tails count as missing)
+  int64_t covered = 0;
+  {
+    int64_t first = (int64_t)lane * 16;
+    if (first < nbytes) covered = ((nbytes - 1 - first) / (64 * 16) + 1) * 64;
+  }
+  int present = (int)(covered - miss);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    n1 += __shfl_xor(n1, off);
+    present += __shfl_xor(present, off);
+  }
+  if (lane == 0) {
+    v4i c = v4i{2 * present - n1, n1, present, 0};
+    v4i* o4 = reinterpret_cast<v4i*>(out);
+    if (accumulate) {
+      v4i o = *o4;
+      c = v4i{o.x + c.x, o.y + c.y, o.z + c.z, 0};
+    }
+    *o4 = c;
+  }
+}
+
+}  // namespace ccc
+
+namespace ccc {
+
 // Tile (I, J), I <= J, of the t-th entry of the row-major upper triangle
 // (diagonal included) of a T x T tile grid.
 __device__ __forceinline__ void tri_tile(int64_t t, int64_t T, int64_t& I, int64_t& J) {

@@ -17,43 +17,9 @@ __global__ __launch_bounds__(256) void count1_kernel(const uint8_t* __restrict__
                                                      int64_t n, int64_t n_f,
                                                      int32_t* __restrict__ counts,
                                                      int accumulate) {
-  const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
-  const uint8_t* r = v + row * ld;
-  const int64_t nbytes = (n_f + 3) / 4;
-  int n1 = 0, miss = 0;
-  for (int64_t ob = (int64_t)lane * 16; ob < nbytes; ob += 64 * 16) {
-    u4 w = load_fields64(r, ob, n_f);
-    unsigned ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      unsigned b0 = ws[s] & kEven, b1 = (ws[s] >> 1) & kEven;
-      n1 += __popc(b0) + __popc(b0 & b1);
-      miss += __popc(b1 & ~b0);
-    }
-  }
-  // fields covered by the loop minus missing ones (masked tails count as missing)
-  int64_t covered = 0;
-  {
-    int64_t first = (int64_t)lane * 16;
-    if (first < nbytes) covered = ((nbytes - 1 - first) / (64 * 16) + 1) * 64;
-  }
-  int present = (int)(covered - miss);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    n1 += __shfl_xor(n1, off);
-    present += __shfl_xor(present, off);
-  }
-  if (lane == 0) {
-    v4i c = v4i{2 * present - n1, n1, present, 0};
-    v4i* out = reinterpret_cast<v4i*>(counts) + row;
-    if (accumulate) {
-      v4i o = *out;
-      c = v4i{o.x + c.x, o.y + c.y, o.z + c.z, 0};
-    }
-    *out = c;
-  }
+  count_row_wave(v + row * ld, n_f, counts + 4 * row, accumulate);
 }
 
 hipError_t launch_count1(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int32_t* counts,

@@ -1,0 +1,307 @@
+// tile2.h -- device bodies of the 2-way tally tiles, shared by the one-shot
+// kernels (mfma2.hip, pop2.hip) and the persistent batched kernel (many.hip).
+//
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ccc {
+namespace tile2 {
+
+// ---------------------------------------------------------------------------
+// int8-MFMA path
+//
+// The tally is a GEMM whose scalar product became a 2x2 table (Sec. 3.1):
+//   C(a,b) = R_a R_b^T,  R_a[i][q] = rho_{i,q}(a) in {0,1,2}.
+// With per-allele counts as int8 operands and int32 accumulation the four
+// products are exact integer GEMMs, so the matrix cores compute the tables
+// directly (4 MACs per comparison).
+//
+// Design (gfx950, wave64):
+//  * No LDS: each lane loads 16 packed bytes (64 fields) of one row per
+//    super-step straight into registers and unpacks them there.  A lane of the
+//    16x16x64 operand holds 16 k-values of one row; since the contraction
+//    only needs A and B to share the k order, lane (row r, group g) takes the
+//    16 fields of packed word s of its 16 bytes for MFMA step s, in the byte
+//    order produced by the unpack below.  Both operands use the same order.
+//  * Unpack of one packed word (16 fields): four shift+mask steps give bytes
+//    holding one 2-bit code each; v_perm_b32 then looks each code up in a
+//    4-byte table (rho(0) = 2,1,0,0 and rho(1) = 0,1,0,2 for codes 00,01,10,11).
+//  * A wave owns a (16 WM) x (16 WN) tile of pairs with 4 accumulator sets
+//    (one per (a,b)); a workgroup is 2 x 2 waves.  With WM = 4, WN = 2 the
+//    accumulators (128 registers) and operands stay in the 256 arch VGPRs, so
+//    two waves share each SIMD and one's unpack overlaps the other's MFMAs.
+//  * Triangle: the row-major upper triangle of (2*BN)-wide square tiles is
+//    enumerated, each square split into two BN-wide column halves (one
+//    workgroup each); waves with no pair i < j return at once.
+//  * Fields past n_f and whole 16-byte pieces past the row stride are turned
+//    into the missing code, which unpacks to zero in both planes.
+// ---------------------------------------------------------------------------
+
+constexpr unsigned kRho0Table = 0x00000102u;  // code 0,1,2,3 -> 2,1,0,0
+constexpr unsigned kRho1Table = 0x02000100u;  // code 0,1,2,3 -> 0,1,0,2
+constexpr unsigned kLow2 = 0x03030303u;
+
+__device__ __forceinline__ void unpack16(unsigned w, v4i& r0, v4i& r1) {
+  unsigned c0 = w & kLow2, c1 = (w >> 2) & kLow2, c2 = (w >> 4) & kLow2, c3 = (w >> 6) & kLow2;
+  r0 = v4i{(int)__builtin_amdgcn_perm(0u, kRho0Table, c0),
+           (int)__builtin_amdgcn_perm(0u, kRho0Table, c1),
+           (int)__builtin_amdgcn_perm(0u, kRho0Table, c2),
+           (int)__builtin_amdgcn_perm(0u, kRho0Table, c3)};
+  r1 = v4i{(int)__builtin_amdgcn_perm(0u, kRho1Table, c0),
+           (int)__builtin_amdgcn_perm(0u, kRho1Table, c1),
+           (int)__builtin_amdgcn_perm(0u, kRho1Table, c2),
+           (int)__builtin_amdgcn_perm(0u, kRho1Table, c3)};
+}
+
+__device__ __forceinline__ unsigned word_of(const u4& x, int s) {
+  return s == 0 ? x.x : (s == 1 ? x.y : (s == 2 ? x.z : x.w));
+}
+
+template <int WM, int WN>
+__device__ __forceinline__ void mma_superstep(const u4 (&pa)[WM], const u4 (&pb)[WN],
+                                              v4i (&acc)[WM][WN][4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    v4i a0[WM], a1[WM], b0[WN], b1[WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m) unpack16(word_of(pa[m], s), a0[m], a1[m]);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) unpack16(word_of(pb[n], s), b0[n], b1[n]);
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int n = 0; n < WN; ++n) {
+        acc[m][n][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0[m], b0[n], acc[m][n][0], 0, 0, 0);
+        acc[m][n][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0[m], b1[n], acc[m][n][1], 0, 0, 0);
+        acc[m][n][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1[m], b0[n], acc[m][n][2], 0, 0, 0);
+        acc[m][n][3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1[m], b1[n], acc[m][n][3], 0, 0, 0);
+      }
+  }
+}
+
+// One wave's (16 WM) x (16 WN) tile of pairs with first row row0 and first
+// column col0 (see the design notes above).  Waves whose tile holds no pair
+// to compute return at once; no barrier is used, so callers may skip waves.
+template <int WM, int WN>
+__device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0, int64_t col0) {
+  const int lane = threadIdx.x & 63;
+  if (row0 >= a.n_a || col0 >= a.n_b) return;
+  if (a.tri && row0 >= col0 + 16 * WN - 1) return;  // no pair i < j in this wave tile
+  const int g = lane >> 4, rl = lane & 15;
+  const uint8_t* pa[WM];
+  const uint8_t* pb[WN];
+#pragma unroll
+  for (int m = 0; m < WM; ++m) {
+    int64_t r = row0 + 16 * m + rl;
+    pa[m] = a.va + (r < a.n_a ? r : a.n_a - 1) * a.lda + 16 * g;
+  }
+#pragma unroll
+  for (int n = 0; n < WN; ++n) {
+    int64_t r = col0 + 16 * n + rl;
+    pb[n] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
+  }
+
+  v4i acc[WM][WN][4];
+#pragma unroll
+  for (int m = 0; m < WM; ++m)
+#pragma unroll
+    for (int n = 0; n < WN; ++n)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[m][n][e] = v4i{0, 0, 0, 0};
+
+  // Super-steps of 256 fields (64 bytes per row).  The first nfull are
+  // entirely inside n_f (so inside the row stride); one masked step follows.
+  const int64_t nfull = a.n_f / 256;
+  const int64_t nbytes = (a.n_f + 3) / 4;
+  u4 ca[WM], cb[WN];
+  if (nfull > 0) {
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = *reinterpret_cast<const u4*>(pa[m]);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = *reinterpret_cast<const u4*>(pb[n]);
+  }
+  for (int64_t s = 0; s < nfull; ++s) {
+    u4 na[WM], nb[WN];
+    const int64_t kn = (s + 1) * 64;
+    if (s + 1 < nfull) {
+#pragma unroll
+      for (int m = 0; m < WM; ++m) na[m] = *reinterpret_cast<const u4*>(pa[m] + kn);
+#pragma unroll
+      for (int n = 0; n < WN; ++n) nb[n] = *reinterpret_cast<const u4*>(pb[n] + kn);
+    }
+    mma_superstep<WM, WN>(ca, cb, acc);
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = na[m];
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = nb[n];
+  }
+  const int64_t kt = nfull * 64;
+  if (kt < nbytes) {
+    // row pointers already include the lane's 16*g byte offset
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = load_fields64(pa[m] - 16 * g, kt + 16 * g, a.n_f);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = load_fields64(pb[n] - 16 * g, kt + 16 * g, a.n_f);
+    mma_superstep<WM, WN>(ca, cb, acc);
+  }
+
+  // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
+#pragma unroll
+  for (int m = 0; m < WM; ++m)
+#pragma unroll
+    for (int n = 0; n < WN; ++n)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = row0 + 16 * m + 4 * g + e;
+        const int64_t j = col0 + 16 * n + rl;
+        if (i >= a.n_a || j >= a.n_b || (a.tri && i >= j)) continue;
+        v4i t = v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]};
+        int64_t p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
+        if (a.accumulate) t = t + *reinterpret_cast<const v4i*>(a.tables + 4 * p);
+        v4i ci = reinterpret_cast<const v4i*>(a.counts_a)[i];
+        v4i cj = reinterpret_cast<const v4i*>(a.counts_b)[j];
+        store_pair(p, t, ci, cj, a.gamma, a.tables, a.ccc);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// popcount path
+//
+// The paper's tally form (Sec. 3.1): per pair of packed words, build one word
+// per tally target with shifts/AND/OR, then count its set bits.  Here each
+// vector's 32 fields become three bit-planes
+//   P = present (code != 10),  O = rho(1) >= 1 (codes 01, 11),  H = rho(1) = 2 (11),
+// so rho(1) = O + H and rho(0) = 2P - rho(1).  Four sums per pair,
+//   c11 = sum rho_i(1) rho_j(1) = pop(Oi&Oj) + pop(Oi&Hj) + pop(Hi&Oj) + pop(Hi&Hj)
+//   s1p = sum rho_i(1) P_j      = pop(Oi&Pj) + pop(Hi&Pj)
+//   sp1 = sum P_i rho_j(1)      = pop(Pi&Oj) + pop(Pi&Hj)
+//   spp = sum P_i P_j           = pop(Pi&Pj)
+// (9 AND + 9 bit-count-and-add per 32 fields), give the table exactly:
+//   C11 = c11, C10 = 2 s1p - c11, C01 = 2 sp1 - c11,
+//   C00 = 4 spp - 2 sp1 - 2 s1p + c11.
+//
+// Workgroup: 256 threads, a 64 x 64 tile of pairs, 4 x 4 pairs per thread.
+// Each stage stages 256 fields of the 128 tile rows as bit-planes in LDS.
+// Planes interleave the fields of two packed words (any order works as long
+// as both vectors of a pair use the same one).
+// ---------------------------------------------------------------------------
+
+constexpr int kTile = 64;
+constexpr int kStageWords = 8;  // 32-field plane words per stage (= 64 bytes per row)
+
+struct Planes {
+  unsigned p, o, h;
+};
+
+// Bit-planes of 32 fields held in two packed words (missing/padding already
+// turned into code 10).
+__device__ __forceinline__ Planes make_planes(unsigned w0, unsigned w1) {
+  unsigned b0 = (w0 & kEven) | ((w1 & kEven) << 1);
+  unsigned b1 = ((w0 >> 1) & kEven) | (((w1 >> 1) & kEven) << 1);
+  Planes r;
+  r.o = b0;
+  r.h = b0 & b1;
+  r.p = ~(b1 & ~b0);
+  return r;
+}
+
+// LDS staging for one 64 x 64 tile (2 sides x 8 plane words x 64 rows).
+struct Pop2Smem {
+  unsigned P[2][kStageWords][kTile];
+  unsigned O[2][kStageWords][kTile];
+  unsigned H[2][kStageWords][kTile];
+};
+
+// The 64 x 64 tile (I, J) of pairs for the whole workgroup (256 threads; every
+// thread must call it, it uses workgroup barriers).
+__device__ __forceinline__ void pop2_block_tile(const Pair2Args& a, int64_t I, int64_t J,
+                                                Pop2Smem& sm) {
+  const int64_t I0 = I * kTile, J0 = J * kTile;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+
+  // loader role: side 0 = A rows, side 1 = B rows; 32 bytes per thread
+  const int side = tid >> 7, lrow = (tid >> 1) & 63, half = tid & 1;
+  const uint8_t* lptr;
+  if (side == 0) {
+    int64_t r = I0 + lrow < a.n_a ? I0 + lrow : a.n_a - 1;
+    lptr = a.va + r * a.lda;
+  } else {
+    int64_t r = J0 + lrow < a.n_b ? J0 + lrow : a.n_b - 1;
+    lptr = a.vb + r * a.ldb;
+  }
+
+  unsigned c11[4][4], s1p[4][4], sp1[4][4], spp[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) c11[r][c] = s1p[r][c] = sp1[r][c] = spp[r][c] = 0;
+
+  const int64_t nbytes = (a.n_f + 3) / 4;
+  for (int64_t kb = 0; kb < nbytes; kb += 4 * kStageWords * 2) {
+    u4 x0 = load_fields64(lptr, kb + 32 * half, a.n_f);
+    u4 x1 = load_fields64(lptr, kb + 32 * half + 16, a.n_f);
+    Planes pl[4] = {make_planes(x0.x, x0.y), make_planes(x0.z, x0.w), make_planes(x1.x, x1.y),
+                    make_planes(x1.z, x1.w)};
+    __syncthreads();  // the previous stage has been consumed
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sm.P[side][half * 4 + k][lrow] = pl[k].p;
+      sm.O[side][half * 4 + k][lrow] = pl[k].o;
+      sm.H[side][half * 4 + k][lrow] = pl[k].h;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int kw = 0; kw < kStageWords; ++kw) {
+      unsigned aP[4], aO[4], aH[4], bP[4], bO[4], bH[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        aP[r] = sm.P[0][kw][ty + 16 * r];
+        aO[r] = sm.O[0][kw][ty + 16 * r];
+        aH[r] = sm.H[0][kw][ty + 16 * r];
+        bP[r] = sm.P[1][kw][tx + 16 * r];
+        bO[r] = sm.O[1][kw][tx + 16 * r];
+        bH[r] = sm.H[1][kw][tx + 16 * r];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          unsigned x = c11[r][c];
+          x += __popc(aO[r] & bO[c]);
+          x += __popc(aO[r] & bH[c]);
+          x += __popc(aH[r] & bO[c]);
+          x += __popc(aH[r] & bH[c]);
+          c11[r][c] = x;
+          s1p[r][c] += __popc(aO[r] & bP[c]) + __popc(aH[r] & bP[c]);
+          sp1[r][c] += __popc(aP[r] & bO[c]) + __popc(aP[r] & bH[c]);
+          spp[r][c] += __popc(aP[r] & bP[c]);
+        }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = I0 + ty + 16 * r;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t j = J0 + tx + 16 * c;
+      if (i >= a.n_a || j >= a.n_b || (a.tri && i >= j)) continue;
+      int x11 = (int)c11[r][c], x1p = (int)s1p[r][c], xp1 = (int)sp1[r][c],
+          xpp = (int)spp[r][c];
+      v4i t = v4i{4 * xpp - 2 * xp1 - 2 * x1p + x11, 2 * xp1 - x11, 2 * x1p - x11, x11};
+      int64_t p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
+      if (a.accumulate) {
+        v4i o = *reinterpret_cast<const v4i*>(a.tables + 4 * p);
+        t = t + o;
+      }
+      v4i ci = reinterpret_cast<const v4i*>(a.counts_a)[i];
+      v4i cj = reinterpret_cast<const v4i*>(a.counts_b)[j];
+      store_pair(p, t, ci, cj, a.gamma, a.tables, a.ccc);
+    }
+  }
+}
+
+}  // namespace tile2
+}  // namespace ccc
