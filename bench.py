@@ -55,6 +55,7 @@ def committed_traffic(kernel_sources, profile):
 
 MFMA2_SOURCES = ["paper_1705_08213_amd/csrc/mfma2.hip", "paper_1705_08213_amd/csrc/tile2.h",
                  "paper_1705_08213_amd/csrc/common.h"]
+MFMA3_SOURCES = ["paper_1705_08213_amd/csrc/mfma3.hip", "paper_1705_08213_amd/csrc/common.h"]
 
 
 def timing_query(lib, name):
@@ -195,8 +196,12 @@ def bench_3way(args, lib):
                config=dict(workload="3-way CCC: n_v=2048 x n_f=16384, Beta/HW, 0.5% missing",
                            n_v=n_v, n_f=n_f, missing=missing, path="mfma"),
                roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                             frac=ach / INT8_PEAK_TOPS, traffic=None, kernel="mfma3_kernel",
-                             kernel_ms=kms))
+                             frac=ach / INT8_PEAK_TOPS,
+                             traffic=committed_traffic(MFMA3_SOURCES,
+                                                       "profiles/mfma3_3way_n2048_f16384.md"),
+                             traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
+                             algorithmic_bytes=n_v * ((n_f + 3) // 4) + 96 * T + 16 * n_v,
+                             kernel="mfma3_kernel", kernel_ms=kms))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_3way(v, n_f, 1)
     return out
