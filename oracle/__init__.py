@@ -20,7 +20,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# CCC_ORACLE_LIB points the tests' mutation check at a deliberately broken copy.
+_SO = os.environ.get("CCC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "ccc_oracle.c")
 
 GAMMA = 2.0 / 3.0

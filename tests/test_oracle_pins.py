@@ -441,3 +441,20 @@ def test_list_forms_match_the_row_forms():
     jb = rng.integers(0, 11, 50)
     lbt, lbc = oracle.pairs_list(v, vb, n_f, ii, jb)
     assert np.array_equal(lbt, tb[ii, jb]) and np.array_equal(lbc, cb[ii, jb])
+
+
+def test_closed_form_3way_asymmetric_entry_order():
+    # i = 00, j = het, k = 11 on every field: only (a,b,c) = (0,b,1) is nonzero,
+    # rho_i(0) rho_j(b) rho_k(1) = 2*1*2 per field -> C = 4 n_f, f = 1/2 and
+    # CCC = 1/2 (1 - 2/3)(1 - 1/3)(1 - 2/3) = 1/27 at entries 4a+2b+c = 1 and 3.
+    n_f = 211
+    v = synth.constant([0, 1, 3], n_f)
+    t, c = oracle.three_way(v, n_f)
+    assert list(t[0]) == [0, 4 * n_f, 0, 4 * n_f, 0, 0, 0, 0]
+    assert close(c[0][1], 1 / 27) and close(c[0][3], 1 / 27)
+    assert all(c[0][e] == 0.0 for e in (0, 2, 4, 5, 6, 7))
+    # k = 00 instead: a=0, c=0 -> entries 0 and 2
+    v2 = synth.constant([0, 1, 0], n_f)
+    t2, c2 = oracle.three_way(v2, n_f)
+    assert list(t2[0]) == [4 * n_f, 0, 4 * n_f, 0, 0, 0, 0, 0]
+    assert close(c2[0][0], 1 / 27) and close(c2[0][2], 1 / 27)
