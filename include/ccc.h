@@ -142,6 +142,57 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
                    int64_t ldb, int64_t n_f, int32_t* tables, int32_t* counts_a,
                    int32_t* counts_b, double* ccc, const ccc_opts* opts, hipStream_t stream);
 
+/*
+ * ccc_2way_rows -- the pairs (i, j) with i_begin <= i < i_end, i < j: a
+ * contiguous run of the lexicographic pair order, so a large result can be
+ * produced in stages (the paper's 2-way "phases", Sec. 7 item 3).  tables /
+ * ccc hold the run only: pair (i, j) goes to entry p(i,j) - p(i_begin,
+ * i_begin+1); the run has p(i_end-1, n_v-1) + 1 - p(i_begin, i_begin+1)
+ * entries (rows i >= n_v - 1 have none).  0 <= i_begin <= i_end <= n_v,
+ * else CCC_ERR_ARG; the rest as ccc_2way (counts cover all n_v vectors).
+ */
+int ccc_2way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_begin,
+                  int64_t i_end, int32_t* tables, double* ccc, int32_t* counts,
+                  const ccc_opts* opts, hipStream_t stream);
+
+/*
+ * ccc_3way_rows -- the triples (i, j, k) with i_begin <= i < i_end: a
+ * contiguous run of the lexicographic triple order (the paper's 3-way
+ * stages, Sec. 4).  Triple t goes to entry t - T(i_begin, i_begin+1,
+ * i_begin+2); otherwise as ccc_3way.
+ */
+int ccc_3way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_begin,
+                  int64_t i_end, int32_t* tables, double* ccc, int32_t* counts,
+                  const ccc_opts* opts, hipStream_t stream);
+
+/*
+ * Threshold-filtered output (the paper's production use keeps only values
+ * above a threshold, Sec. 7 item 6).  A pair (triple) is kept when at least
+ * one of its 4 (8) CCC values is >= threshold; each kept one takes a slot from
+ * the device counter `count` and, if the slot is below `cap`, writes
+ *   index[slot]  = its pair index p(i,j) (triple index T(i,j,k)),
+ *   ccc[slot]    = its CCC values (4 or 8 doubles),
+ *   tables[slot] = its table (4 or 8 int32; skipped when tables is NULL).
+ * After the call *count holds the number of kept pairs (triples); when it
+ * exceeds cap only cap records were written.  Slot order is unspecified (it
+ * depends on scheduling); the set of records is deterministic.  All pointers
+ * are device pointers, 16-byte aligned; the library clears *count itself.
+ */
+typedef struct {
+  int64_t* index;
+  double* ccc;
+  int32_t* tables;
+  int64_t cap;
+  unsigned long long* count;
+} ccc_selection;
+
+int ccc_2way_select(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, double threshold,
+                    const ccc_selection* out, int32_t* counts, const ccc_opts* opts,
+                    hipStream_t stream);
+int ccc_3way_select(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, double threshold,
+                    const ccc_selection* out, int32_t* counts, const ccc_opts* opts,
+                    hipStream_t stream);
+
 /* One independent 2-way problem for ccc_2way_many (same meaning as ccc_2way). */
 typedef struct {
   const uint8_t* v;

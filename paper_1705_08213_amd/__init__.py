@@ -40,6 +40,11 @@ class ccc_opts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int), ("gamma", ctypes.c_double), ("flags", ctypes.c_uint)]
 
 
+class ccc_selection(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_void_p), ("ccc", ctypes.c_void_p), ("tables", ctypes.c_void_p),
+                ("cap", ctypes.c_int64), ("count", ctypes.c_void_p)]
+
+
 class ccc_problem(ctypes.Structure):
     _fields_ = [("v", ctypes.c_void_p), ("n_v", ctypes.c_int64), ("n_f", ctypes.c_int64),
                 ("ld", ctypes.c_int64), ("tables", ctypes.c_void_p), ("ccc", ctypes.c_void_p),
@@ -62,8 +67,17 @@ def lib():
         L.ccc_3way.argtypes = [vp, i64, i64, i64, vp, vp, vp, opts_p, vp]
         L.ccc_2way_block.argtypes = [vp, i64, i64, vp, i64, i64, i64, vp, vp, vp, vp, opts_p, vp]
         L.ccc_2way_many.argtypes = [ctypes.POINTER(ccc_problem), cint, opts_p, vp]
-        for f in (L.ccc_2way, L.ccc_3way, L.ccc_2way_block, L.ccc_2way_many):
+        L.ccc_2way_rows.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp, vp, opts_p, vp]
+        L.ccc_3way_rows.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp, vp, opts_p, vp]
+        sel_p = ctypes.POINTER(ccc_selection)
+        L.ccc_2way_select.argtypes = [vp, i64, i64, i64, ctypes.c_double, sel_p, vp, opts_p, vp]
+        L.ccc_3way_select.argtypes = [vp, i64, i64, i64, ctypes.c_double, sel_p, vp, opts_p, vp]
+        for f in (L.ccc_2way, L.ccc_3way, L.ccc_2way_block, L.ccc_2way_many, L.ccc_2way_rows,
+                  L.ccc_3way_rows, L.ccc_2way_select, L.ccc_3way_select):
             f.restype = cint
+        L.ccc_timing_enable.argtypes = [cint]
+        L.ccc_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(cint)]
+        L.ccc_timing_query.restype = ctypes.c_double
         L.ccc_status_string.argtypes = [cint]
         L.ccc_status_string.restype = ctypes.c_char_p
         L.ccc_version.restype = cint
@@ -193,6 +207,100 @@ def ccc_3way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMM
                         ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_3way")
     return tables, ccc, counts
+
+
+def pair_run_length(n_v: int, i_begin: int, i_end: int) -> int:
+    """Number of pairs (i, j), i_begin <= i < i_end, i < j < n_v."""
+    return sum(max(n_v - 1 - i, 0) for i in range(i_begin, min(i_end, n_v)))
+
+
+def triple_run_length(n_v: int, i_begin: int, i_end: int) -> int:
+    """Number of triples (i, j, k), i_begin <= i < i_end, i < j < k < n_v."""
+    return sum(n_pairs(n_v - 1 - i) for i in range(i_begin, min(i_end, n_v)))
+
+
+def ccc_2way_rows(v, n_f, i_begin, i_end, tables=None, ccc=None, counts=None, path="auto",
+                  gamma=GAMMA, want_tables=True, want_ccc=True, stream=None):
+    """Pairs with first index in [i_begin, i_end), in lexicographic order."""
+    torch = _torch()
+    _check_input(v)
+    n_v, ld = v.shape
+    P = pair_run_length(n_v, i_begin, i_end)
+    dev = v.device
+    if tables is None and want_tables:
+        tables = torch.empty((P, 4), dtype=torch.int32, device=dev)
+    if ccc is None and want_ccc:
+        ccc = torch.empty((P, 4), dtype=torch.float64, device=dev)
+    if counts is None:
+        counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
+    _check_out(tables, (P, 4), torch.int32, "tables")
+    _check_out(ccc, (P, 4), torch.float64, "ccc")
+    o = make_opts(path, gamma)
+    st = lib().ccc_2way_rows(_ptr(v), n_v, n_f, ld, i_begin, i_end, _ptr(tables), _ptr(ccc),
+                             _ptr(counts), ctypes.byref(o), _stream(stream))
+    _raise(st, "ccc_2way_rows")
+    return tables, ccc, counts
+
+
+def ccc_3way_rows(v, n_f, i_begin, i_end, tables=None, ccc=None, counts=None, path="auto",
+                  gamma=GAMMA, want_tables=True, want_ccc=True, stream=None):
+    """Triples with first index in [i_begin, i_end), in lexicographic order."""
+    torch = _torch()
+    _check_input(v)
+    n_v, ld = v.shape
+    T = triple_run_length(n_v, i_begin, i_end)
+    dev = v.device
+    if tables is None and want_tables:
+        tables = torch.empty((T, 8), dtype=torch.int32, device=dev)
+    if ccc is None and want_ccc:
+        ccc = torch.empty((T, 8), dtype=torch.float64, device=dev)
+    if counts is None:
+        counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
+    _check_out(tables, (T, 8), torch.int32, "tables")
+    _check_out(ccc, (T, 8), torch.float64, "ccc")
+    o = make_opts(path, gamma)
+    st = lib().ccc_3way_rows(_ptr(v), n_v, n_f, ld, i_begin, i_end, _ptr(tables), _ptr(ccc),
+                             _ptr(counts), ctypes.byref(o), _stream(stream))
+    _raise(st, "ccc_3way_rows")
+    return tables, ccc, counts
+
+
+def _select(fn_name, width, v, n_f, threshold, cap, with_tables, counts, path, gamma, stream):
+    torch = _torch()
+    _check_input(v)
+    n_v, ld = v.shape
+    dev = v.device
+    index = torch.empty((max(cap, 1),), dtype=torch.int64, device=dev)
+    cc = torch.empty((max(cap, 1), width), dtype=torch.float64, device=dev)
+    tables = torch.empty((max(cap, 1), width), dtype=torch.int32, device=dev) if with_tables else None
+    count = torch.zeros((2,), dtype=torch.int64, device=dev)  # 16-byte aligned counter
+    if counts is None:
+        counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
+    sel = ccc_selection(index.data_ptr(), cc.data_ptr(),
+                        tables.data_ptr() if tables is not None else None, cap, count.data_ptr())
+    o = make_opts(path, gamma)
+    st = getattr(lib(), fn_name)(_ptr(v), n_v, n_f, ld, float(threshold), ctypes.byref(sel),
+                                 _ptr(counts), ctypes.byref(o), _stream(stream))
+    _raise(st, fn_name)
+    n = int(count[0].item())
+    k = min(n, cap)
+    return n, index[:k], cc[:k], (tables[:k] if tables is not None else None)
+
+
+def ccc_2way_select(v, n_f, threshold, cap, with_tables=True, counts=None, path="auto",
+                    gamma=GAMMA, stream=None):
+    """Pairs with some CCC value >= threshold: (number found, pair index [k], CCC [k, 4],
+    tables [k, 4]) with k = min(found, cap), in unspecified order.  Synchronises to read
+    the count."""
+    return _select("ccc_2way_select", 4, v, n_f, threshold, cap, with_tables, counts, path,
+                   gamma, stream)
+
+
+def ccc_3way_select(v, n_f, threshold, cap, with_tables=True, counts=None, path="auto",
+                    gamma=GAMMA, stream=None):
+    """Triples with some CCC value >= threshold (see ccc_2way_select)."""
+    return _select("ccc_3way_select", 8, v, n_f, threshold, cap, with_tables, counts, path,
+                   gamma, stream)
 
 
 def ccc_2way_block(va, vb, n_f, tables, counts_a, counts_b, ccc=None, accumulate=False,

@@ -110,21 +110,45 @@ const char* ccc_status_string(int status) {
   }
 }
 
-int ccc_2way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
-             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// All 2-way variants: dense rows [i_begin, i_end) (tables/ccc) or selection.
+int two_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_begin,
+            int64_t i_end, int32_t* tables, double* ccc, const ccc_selection* sel,
+            double threshold, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
   ccc_opts o;
   int st = resolve_opts(opts, &o);
   if (st) return st;
   if (o.flags != 0) return CCC_ERR_ARG;
   if ((st = check_input(v, n_v, n_f, ld))) return st;
   if (4 * n_f > kInt32Max) return CCC_ERR_RANGE;
-  if (n_v >= 2 && !tables && !ccc) return CCC_ERR_ARG;
+  if (i_begin < 0 || i_end < i_begin || i_end > n_v) return CCC_ERR_ARG;
+  if (sel) {
+    if (!sel->index || !sel->ccc || !sel->count || sel->cap < 0) return CCC_ERR_ARG;
+    if (!isfinite(threshold)) return CCC_ERR_ARG;
+    if (!aligned16(sel->index) || !aligned16(sel->ccc) || !aligned16(sel->tables) ||
+        !aligned16(sel->count))
+      return CCC_ERR_ALIGN;
+  } else if ((i_end < n_v - 1 ? i_end : n_v - 1) > i_begin && !tables && !ccc) {
+    return CCC_ERR_ARG;  // the range holds pairs but there is nowhere to put them
+  }
   if (!aligned16(tables) || !aligned16(ccc) || !aligned16(counts)) return CCC_ERR_ALIGN;
   if (n_v == 0) return CCC_OK;
+  unsigned long long* zero = sel ? sel->count : nullptr;
+  const int64_t row_end = i_end < n_v - 1 ? i_end : n_v - 1;  // the last row has no pair
+  if (row_end <= i_begin && !counts && !zero) return CCC_OK;  // nothing to compute or write
   if (n_v == 1) {
-    if (!counts) return CCC_OK;
-    return ccc::launch_count1(v, ld, n_v, n_f, counts, 0, stream) == hipSuccess ? CCC_OK
-                                                                                  : CCC_ERR_HIP;
+    if (!counts && !zero) return CCC_OK;
+    if (!counts) {  // only the selection counter to clear
+      void* ws = nullptr;
+      if ((st = ccc::workspace(16, &ws))) return st;
+      counts = static_cast<int32_t*>(ws);
+    }
+    return ccc::launch_count1_zero(v, ld, n_v, n_f, counts, 0, zero, stream) == hipSuccess
+               ? CCC_OK
+               : CCC_ERR_HIP;
   }
   int32_t* cnt = counts;
   if (!cnt) {
@@ -132,7 +156,9 @@ int ccc_2way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* ta
     if ((st = ccc::workspace((size_t)n_v * 16, &ws))) return st;
     cnt = static_cast<int32_t*>(ws);
   }
-  if (ccc::launch_count1(v, ld, n_v, n_f, cnt, 0, stream) != hipSuccess) return CCC_ERR_HIP;
+  if (ccc::launch_count1_zero(v, ld, n_v, n_f, cnt, 0, zero, stream) != hipSuccess)
+    return CCC_ERR_HIP;
+  if (row_end <= i_begin) return CCC_OK;
   ccc::Pair2Args a{};
   a.va = v; a.lda = ld; a.n_a = n_v;
   a.vb = v; a.ldb = ld; a.n_b = n_v;
@@ -144,32 +170,55 @@ int ccc_2way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* ta
   a.counts_a = cnt;
   a.counts_b = cnt;
   a.gamma = o.gamma;
+  a.row_begin = i_begin;
+  a.row_end = row_end;
+  a.p_base = i_begin * n_v - i_begin * (i_begin + 1) / 2;  // p(i_begin, i_begin + 1)
+  a.sel = sel ? ccc::Select{sel->count, sel->cap, threshold, sel->index, sel->ccc, sel->tables}
+              : ccc::Select{nullptr, 0, 0.0, nullptr, nullptr, nullptr};
   return ccc::run_pair2(a, o.path, stream);
 }
 
-int ccc_3way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
-             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+int64_t choose3(int64_t n) { return n < 3 ? 0 : n * (n - 1) / 2 * (n - 2) / 3; }
+int64_t choose2(int64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
+
+// All 3-way variants: dense first-index rows [i_begin, i_end) or selection.
+int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_begin,
+              int64_t i_end, int32_t* tables, double* ccc, const ccc_selection* sel,
+              double threshold, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
   ccc_opts o;
   int st = resolve_opts(opts, &o);
   if (st) return st;
   if (o.flags != 0) return CCC_ERR_ARG;
   if ((st = check_input(v, n_v, n_f, ld))) return st;
   if (8 * n_f > kInt32Max) return CCC_ERR_RANGE;
-  if (n_v >= 3 && !tables && !ccc) return CCC_ERR_ARG;
+  if (i_begin < 0 || i_end < i_begin || i_end > n_v) return CCC_ERR_ARG;
+  if (sel) {
+    if (!sel->index || !sel->ccc || !sel->count || sel->cap < 0) return CCC_ERR_ARG;
+    if (!isfinite(threshold)) return CCC_ERR_ARG;
+    if (!aligned16(sel->index) || !aligned16(sel->ccc) || !aligned16(sel->tables) ||
+        !aligned16(sel->count))
+      return CCC_ERR_ALIGN;
+  } else if ((i_end < n_v - 2 ? i_end : n_v - 2) > i_begin && !tables && !ccc) {
+    return CCC_ERR_ARG;  // the range holds triples but there is nowhere to put them
+  }
   if (!aligned16(tables) || !aligned16(ccc) || !aligned16(counts)) return CCC_ERR_ALIGN;
   if (n_v > 2642245) return CCC_ERR_ARG;  // C(n_v,3) * 8 must fit int64 indexing
   if (n_v == 0) return CCC_OK;
-  if (n_v < 3) {
-    if (!counts) return CCC_OK;
-    return ccc::launch_count1(v, ld, n_v, n_f, counts, 0, stream) == hipSuccess ? CCC_OK
-                                                                                  : CCC_ERR_HIP;
-  }
+  unsigned long long* zero = sel ? sel->count : nullptr;
+  const int64_t row_end = i_end < n_v - 2 ? i_end : n_v - 2;  // first index below n_v - 2
+  if (row_end <= i_begin && !counts && !zero) return CCC_OK;  // nothing to compute or write
   // workspace: offsets of the tetrahedral work units, then (if needed) counts
   const size_t offs_bytes = ((size_t)(n_v + 1) * 8 + 255) / 256 * 256;
   void* ws = nullptr;
   if ((st = ccc::workspace(offs_bytes + (counts ? 0 : (size_t)n_v * 16), &ws))) return st;
   int32_t* cnt = counts ? counts : reinterpret_cast<int32_t*>(static_cast<char*>(ws) + offs_bytes);
-  if (ccc::launch_count1(v, ld, n_v, n_f, cnt, 0, stream) != hipSuccess) return CCC_ERR_HIP;
+  if (n_v < 3)
+    return ccc::launch_count1_zero(v, ld, n_v, n_f, cnt, 0, zero, stream) == hipSuccess
+               ? CCC_OK
+               : CCC_ERR_HIP;
+  if (ccc::launch_count1_zero(v, ld, n_v, n_f, cnt, 0, zero, stream) != hipSuccess)
+    return CCC_ERR_HIP;
+  if (row_end <= i_begin) return CCC_OK;
   ccc::Triple3Args a{};
   a.v = v; a.ld = ld; a.n = n_v; a.n_f = n_f;
   a.tables = tables;
@@ -177,9 +226,60 @@ int ccc_3way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* ta
   a.counts = cnt;
   a.gamma = o.gamma;
   a.offs = static_cast<int64_t*>(ws);
+  a.i_begin = i_begin;
+  a.i_end = row_end;
+  a.t_base = choose3(n_v) - choose3(n_v - i_begin);  // T(i_begin, i_begin+1, i_begin+2)
+  a.sel = sel ? ccc::Select{sel->count, sel->cap, threshold, sel->index, sel->ccc, sel->tables}
+              : ccc::Select{nullptr, 0, 0.0, nullptr, nullptr, nullptr};
   hipError_t e = o.path == CCC_PATH_POPCOUNT ? ccc::launch_pop3(a, stream)
                                              : ccc::launch_mfma3(a, stream);
   return e == hipSuccess ? CCC_OK : CCC_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ccc_2way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+  return two_way(v, n_v, n_f, ld, 0, n_v < 0 ? 0 : n_v, tables, ccc, nullptr, 0.0, counts, opts,
+                 stream);
+}
+
+int ccc_2way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_begin,
+                  int64_t i_end, int32_t* tables, double* ccc, int32_t* counts,
+                  const ccc_opts* opts, hipStream_t stream) {
+  return two_way(v, n_v, n_f, ld, i_begin, i_end, tables, ccc, nullptr, 0.0, counts, opts,
+                 stream);
+}
+
+int ccc_2way_select(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, double threshold,
+                    const ccc_selection* out, int32_t* counts, const ccc_opts* opts,
+                    hipStream_t stream) {
+  if (!out) return CCC_ERR_ARG;
+  return two_way(v, n_v, n_f, ld, 0, n_v < 0 ? 0 : n_v, nullptr, nullptr, out, threshold,
+                 counts, opts, stream);
+}
+
+int ccc_3way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_begin,
+                  int64_t i_end, int32_t* tables, double* ccc, int32_t* counts,
+                  const ccc_opts* opts, hipStream_t stream) {
+  return three_way(v, n_v, n_f, ld, i_begin, i_end, tables, ccc, nullptr, 0.0, counts, opts,
+                   stream);
+}
+
+int ccc_3way_select(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, double threshold,
+                    const ccc_selection* out, int32_t* counts, const ccc_opts* opts,
+                    hipStream_t stream) {
+  if (!out) return CCC_ERR_ARG;
+  return three_way(v, n_v, n_f, ld, 0, n_v < 0 ? 0 : n_v, nullptr, nullptr, out, threshold,
+                   counts, opts, stream);
+}
+
+int ccc_3way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+             double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+  return three_way(v, n_v, n_f, ld, 0, n_v < 0 ? 0 : n_v, tables, ccc, nullptr, 0.0, counts,
+                   opts, stream);
 }
 
 int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* vb, int64_t n_b,
@@ -214,6 +314,10 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   a.counts_a = counts_a;
   a.counts_b = counts_b;
   a.gamma = o.gamma;
+  a.row_begin = 0;
+  a.row_end = n_a;
+  a.p_base = 0;
+  a.sel = ccc::Select{nullptr, 0, 0.0, nullptr, nullptr, nullptr};
   return ccc::run_pair2(a, o.path, stream);
 }
 

@@ -78,33 +78,52 @@ __device__ __forceinline__ double one_minus_gf(int n_a, int m, double gamma) {
   return 1.0 - gamma * f;
 }
 
-// 2-way epilogue for one pair (Eqs. (2)-(3)): t = (C00, C01, C10, C11),
-// ci / cj = (n(0), n(1), m, 0) of the two vectors.  Writes the table (if
-// `tables`) and the CCC values (if `ccc`) of entry p.
+// CCC of one pair (Eqs. (2)-(3)) from its table t = (C00, C01, C10, C11) and
+// the counts (n(0), n(1), m, 0) of the two vectors; all zero when m_ij = 0.
+__device__ __forceinline__ void pair_ccc(v4i t, v4i ci, v4i cj, double gamma, double (&r)[4]) {
+#pragma clang fp contract(off)
+  int sum = t.x + t.y + t.z + t.w;
+  int m_ij = sum >> 2;  // fields where both are present
+  if (m_ij > 0) {
+    double den = 4.0 * (double)m_ij;
+    double wi0 = one_minus_gf(ci.x, ci.z, gamma), wi1 = one_minus_gf(ci.y, ci.z, gamma);
+    double wj0 = one_minus_gf(cj.x, cj.z, gamma), wj1 = one_minus_gf(cj.y, cj.z, gamma);
+    r[0] = ((double)t.x / den) * wi0 * wj0;
+    r[1] = ((double)t.y / den) * wi0 * wj1;
+    r[2] = ((double)t.z / den) * wi1 * wj0;
+    r[3] = ((double)t.w / den) * wi1 * wj1;
+  } else {
+    r[0] = r[1] = r[2] = r[3] = 0.0;
+  }
+}
+
+// Dense 2-way store of entry p: the table (if `tables`) and CCC (if `ccc`).
 __device__ __forceinline__ void store_pair(int64_t p, v4i t, v4i ci, v4i cj, double gamma,
                                            int32_t* __restrict__ tables,
                                            double* __restrict__ ccc) {
-#pragma clang fp contract(off)
   if (tables) *reinterpret_cast<v4i*>(tables + 4 * p) = t;
   if (ccc) {
-    int sum = t.x + t.y + t.z + t.w;
-    int m_ij = sum >> 2;  // fields where both are present
-    double r0, r1, r2, r3;
-    if (m_ij > 0) {
-      double den = 4.0 * (double)m_ij;
-      double wi0 = one_minus_gf(ci.x, ci.z, gamma), wi1 = one_minus_gf(ci.y, ci.z, gamma);
-      double wj0 = one_minus_gf(cj.x, cj.z, gamma), wj1 = one_minus_gf(cj.y, cj.z, gamma);
-      r0 = ((double)t.x / den) * wi0 * wj0;
-      r1 = ((double)t.y / den) * wi0 * wj1;
-      r2 = ((double)t.z / den) * wi1 * wj0;
-      r3 = ((double)t.w / den) * wi1 * wj1;
-    } else {
-      r0 = r1 = r2 = r3 = 0.0;
-    }
+    double r[4];
+    pair_ccc(t, ci, cj, gamma, r);
     double2* out = reinterpret_cast<double2*>(ccc + 4 * p);
-    out[0] = double2{r0, r1};
-    out[1] = double2{r2, r3};
+    out[0] = double2{r[0], r[1]};
+    out[1] = double2{r[2], r[3]};
   }
+}
+
+// Slot for this lane's record in a selection buffer: one atomic per wave
+// (ballot of the lanes that keep a record); every lane of the wave must call
+// it.  Returns -1 for lanes that keep nothing.
+__device__ __forceinline__ int64_t select_slot(bool keep, unsigned long long* count) {
+  const unsigned long long mask = __ballot(keep ? 1 : 0);
+  if (mask == 0ull) return -1;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  if (!keep) return -1;
+  return (int64_t)(base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull)));
 }
 
 }  // namespace ccc
@@ -179,16 +198,22 @@ namespace ccc {
 // I tiles [0, ceil(j/bi)) (rows below j) times the K tiles
 // [floor((j+1)/bk), ceil(n/bk)) (columns above j).
 // ---------------------------------------------------------------------------
+// Only I tiles meeting rows [i_begin, min(j, i_end)) are kept (a staged
+// range of first indices).
 __host__ __device__ __forceinline__ int64_t units_for_j(int64_t j, int64_t n, int64_t bi,
-                                                        int64_t bk) {
-  if (j < 1 || j > n - 2) return 0;
-  int64_t ni = (j + bi - 1) / bi;
+                                                        int64_t bk, int64_t i_begin,
+                                                        int64_t i_end) {
+  if (j < 1 || j > n - 2 || j <= i_begin) return 0;
+  const int64_t hi = j < i_end ? j : i_end;
+  if (hi <= i_begin) return 0;
+  int64_t ni = (hi + bi - 1) / bi - i_begin / bi;
   int64_t nk = (n + bk - 1) / bk - (j + 1) / bk;
   return ni * nk;
 }
 
 // Unit u -> (j, I tile, K tile), given offs[j] = units of all j' < j (j = 0..n).
 __device__ __forceinline__ void unit_coords(int64_t u, int64_t n, int64_t bi, int64_t bk,
+                                            int64_t i_begin, int64_t i_end,
                                             const int64_t* __restrict__ offs, int64_t& j,
                                             int64_t& it, int64_t& kt) {
   int64_t lo = 0, hi = n;  // offs[lo] <= u < offs[hi]
@@ -198,8 +223,9 @@ __device__ __forceinline__ void unit_coords(int64_t u, int64_t n, int64_t bi, in
   }
   j = lo;
   const int64_t r = u - offs[j];
-  const int64_t ni = (j + bi - 1) / bi;
-  it = r % ni;
+  const int64_t top = j < i_end ? j : i_end;
+  const int64_t ni = (top + bi - 1) / bi - i_begin / bi;
+  it = i_begin / bi + r % ni;
   kt = (j + 1) / bk + r / ni;
 }
 
@@ -213,14 +239,14 @@ void timing_end(hipStream_t stream);
 namespace {
 
 // offs[j] = number of units of all j' < j, for j = 0..n (one workgroup).
-__global__ void unit_offsets_kernel(int64_t n, int64_t bi, int64_t bk,
-                                    int64_t* __restrict__ offs) {
+__global__ void unit_offsets_kernel(int64_t n, int64_t bi, int64_t bk, int64_t i_begin,
+                                    int64_t i_end, int64_t* __restrict__ offs) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
   const int64_t per = (n + 1 + 1023) / 1024;
   const int64_t lo = t * per, hi = lo + per < n + 1 ? lo + per : n + 1;
   int64_t s = 0;
-  for (int64_t j = lo; j < hi; ++j) s += units_for_j(j, n, bi, bk);
+  for (int64_t j = lo; j < hi; ++j) s += units_for_j(j, n, bi, bk, i_begin, i_end);
   part[t] = s;
   __syncthreads();
   if (t == 0) {
@@ -235,7 +261,7 @@ __global__ void unit_offsets_kernel(int64_t n, int64_t bi, int64_t bk,
   int64_t run = part[t];
   for (int64_t j = lo; j < hi; ++j) {
     offs[j] = run;
-    run += units_for_j(j, n, bi, bk);
+    run += units_for_j(j, n, bi, bk, i_begin, i_end);
   }
 }
 
@@ -245,9 +271,10 @@ template <typename Kernel, typename Args>
 hipError_t launch_units(Kernel kernel, const Args& a, int64_t bi, int64_t bk, const char* name,
                         hipStream_t stream) {
   int64_t total = 0;
-  for (int64_t j = 0; j < a.n; ++j) total += units_for_j(j, a.n, bi, bk);
+  for (int64_t j = 0; j < a.n; ++j) total += units_for_j(j, a.n, bi, bk, a.i_begin, a.i_end);
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(unit_offsets_kernel, dim3(1), dim3(1024), 0, stream, a.n, bi, bk, a.offs);
+  hipLaunchKernelGGL(unit_offsets_kernel, dim3(1), dim3(1024), 0, stream, a.n, bi, bk, a.i_begin,
+                     a.i_end, a.offs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t kMaxGrid = 0x40000000;

@@ -92,6 +92,11 @@ __device__ __forceinline__ Pair2Args pair_args(const ProbDesc& p, double gamma) 
   a.counts_a = p.counts;
   a.counts_b = p.counts;
   a.gamma = gamma;
+  a.row_begin = 0;
+  a.row_end = p.n_v;
+  a.p_base = 0;
+  a.sq_offset = 0;
+  a.sel = Select{nullptr, 0, 0.0, nullptr, nullptr, nullptr};
   return a;
 }
 

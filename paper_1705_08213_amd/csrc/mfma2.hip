@@ -16,7 +16,7 @@ __global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tile
   int64_t I, J;
   if (a.tri) {
     int64_t sq_i, sq_j;
-    tri_tile(blockIdx.x >> 1, tiles_side, sq_i, sq_j);
+    tri_tile((blockIdx.x >> 1) + a.sq_offset, tiles_side, sq_i, sq_j);
     I = sq_i;
     J = 2 * sq_j + (blockIdx.x & 1);
   } else {
@@ -30,11 +30,17 @@ template <int WM, int WN>
 hipError_t launch_shape(const Pair2Args& a, hipStream_t stream) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   int64_t tm = (a.n_a + BM - 1) / BM, tn = (a.n_b + BN - 1) / BN;
-  int64_t ntiles = a.tri ? tm * (tm + 1) : tm * tn;  // triangle: two halves per square
+  int64_t ntiles = tm * tn;
+  Pair2Args b = a;
+  if (a.tri) {  // squares of the row range, two halves each
+    const int64_t s0 = a.row_begin / BM, s1 = (a.row_end + BM - 1) / BM;
+    b.sq_offset = s0 * tm - s0 * (s0 - 1) / 2;
+    ntiles = 2 * (s1 * tm - s1 * (s1 - 1) / 2 - b.sq_offset);
+  }
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   timing_begin("mfma2", stream);
-  hipLaunchKernelGGL((mfma2_kernel<WM, WN>), dim3((unsigned)ntiles), dim3(256), 0, stream, a, tm,
+  hipLaunchKernelGGL((mfma2_kernel<WM, WN>), dim3((unsigned)ntiles), dim3(256), 0, stream, b, tm,
                      tn);
   timing_end(stream);
   return hipGetLastError();

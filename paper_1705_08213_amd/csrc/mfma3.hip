@@ -19,8 +19,7 @@
 // tile columns above j (tetrahedral: only i < j < k is ever stored).  A
 // workgroup is 2 x 2 waves over a (32 WI) x (32 WK) tile for one j; waves
 // whose whole tile has no valid (i, k) exit at once.
-#include "common.h"
-#include "kernels.h"
+#include "tile3.h"
 
 namespace ccc {
 
@@ -58,7 +57,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a,
   const int64_t n = a.n;
   const int64_t u = unit_base + blockIdx.x;
   int64_t j, it, kt;
-  unit_coords(u, n, BI, BK, offs, j, it, kt);
+  unit_coords(u, n, BI, BK, a.i_begin, a.i_end, offs, j, it, kt);
 
   const int64_t row0 = it * BI + (wave & 1) * 16 * WI;  // i range of this wave
   const int64_t col0 = kt * BK + (wave >> 1) * 16 * WK; // k range of this wave
@@ -154,55 +153,23 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a,
   }
 
   // Epilogue: entry 4a + 2b + c; lane holds rows 4g + e of column rl.
-  const v4i cjv = reinterpret_cast<const v4i*>(a.counts)[j];
-  double wj0 = one_minus_gf(cjv.x, cjv.z, a.gamma), wj1 = one_minus_gf(cjv.y, cjv.z, a.gamma);
+  double wj[2];
+  vector_factors(a.counts, j, a.gamma, wj);
 #pragma unroll
   for (int m = 0; m < WI; ++m)
 #pragma unroll
     for (int c = 0; c < WK; ++c) {
       const int64_t k = col0 + 16 * c + rl;
-      if (k <= j || k >= n) continue;
-      const v4i ckv = reinterpret_cast<const v4i*>(a.counts)[k];
-      const double wk0 = one_minus_gf(ckv.x, ckv.z, a.gamma);
-      const double wk1 = one_minus_gf(ckv.y, ckv.z, a.gamma);
+      const bool kvalid = k > j && k < n;
+      double wk[2];
+      vector_factors(a.counts, kvalid ? k : j, a.gamma, wk);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i = row0 + 16 * m + 4 * g + e;
-        if (i >= j) continue;
         int t[8];
 #pragma unroll
         for (int x = 0; x < 8; ++x) t[x] = acc[m][c][x][e];
-        const int64_t p = triple_index(n, i, j, k);
-        if (a.tables) {
-          v4i* out = reinterpret_cast<v4i*>(a.tables + 8 * p);
-          out[0] = v4i{t[0], t[1], t[2], t[3]};
-          out[1] = v4i{t[4], t[5], t[6], t[7]};
-        }
-        if (a.ccc) {
-          int sum = 0;
-#pragma unroll
-          for (int x = 0; x < 8; ++x) sum += t[x];
-          const int m_ijk = sum >> 3;
-          double r[8];
-          if (m_ijk > 0) {
-            const v4i civ = reinterpret_cast<const v4i*>(a.counts)[i];
-            const double wi[2] = {one_minus_gf(civ.x, civ.z, a.gamma),
-                                  one_minus_gf(civ.y, civ.z, a.gamma)};
-            const double wj[2] = {wj0, wj1}, wk[2] = {wk0, wk1};
-            const double den = 8.0 * (double)m_ijk;
-#pragma unroll
-            for (int x = 0; x < 8; ++x)
-              r[x] = ((double)t[x] / den) * wi[x >> 2] * wj[(x >> 1) & 1] * wk[x & 1];
-          } else {
-#pragma unroll
-            for (int x = 0; x < 8; ++x) r[x] = 0.0;
-          }
-          double2* out = reinterpret_cast<double2*>(a.ccc + 8 * p);
-          out[0] = double2{r[0], r[1]};
-          out[1] = double2{r[2], r[3]};
-          out[2] = double2{r[4], r[5]};
-          out[3] = double2{r[6], r[7]};
-        }
+        emit_triple(a, kvalid && i < j, i, j, k, t, wj, wk);
       }
     }
 }

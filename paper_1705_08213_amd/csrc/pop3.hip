@@ -11,8 +11,7 @@
 // Same tetrahedral work units as the MFMA kernel, with 64 x 64 (i, k) tiles
 // and 4 x 4 triples per thread; the 129 tile rows (64 i, 64 k and j) are
 // staged as planes in LDS, 256 fields at a time.
-#include "common.h"
-#include "kernels.h"
+#include "tile3.h"
 
 namespace ccc {
 
@@ -39,7 +38,7 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
 
   const int64_t n = a.n;
   int64_t j, it, kt;
-  unit_coords(unit_base + blockIdx.x, n, kTile, kTile, offs, j, it, kt);
+  unit_coords(unit_base + blockIdx.x, n, kTile, kTile, a.i_begin, a.i_end, offs, j, it, kt);
   const int64_t I0 = it * kTile, K0 = kt * kTile;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
 
@@ -120,22 +119,23 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
     }
   }
 
-  const v4i cjv = reinterpret_cast<const v4i*>(a.counts)[j];
-  const double wj[2] = {one_minus_gf(cjv.x, cjv.z, a.gamma), one_minus_gf(cjv.y, cjv.z, a.gamma)};
+  double wj[2];
+  vector_factors(a.counts, j, a.gamma, wj);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t i = I0 + ty + 16 * r;
-    if (i >= j) continue;
+  for (int c = 0; c < 4; ++c) {
+    const int64_t k = K0 + tx + 16 * c;
+    const bool kvalid = k > j && k < n;
+    double wk[2];
+    vector_factors(a.counts, kvalid ? k : j, a.gamma, wk);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t k = K0 + tx + 16 * c;
-      if (k <= j || k >= n) continue;
-      // w_0 = (2, -1), w_1 = (0, 1) over (P, R)
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = I0 + ty + 16 * r;
+      // w_0 = (2, -1), w_1 = (0, 1) over (P, R); unsigned: partial sums may
+      // leave the int32 range, the total fits
       int tab[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int aa = e >> 2, bb = (e >> 1) & 1, cc = e & 1;
-        // unsigned: partial sums may leave the int32 range; the total fits
         unsigned s = 0;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -150,39 +150,7 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
             }
         tab[e] = (int)s;
       }
-      const int64_t p = triple_index(n, i, j, k);
-      if (a.tables) {
-        v4i* out = reinterpret_cast<v4i*>(a.tables + 8 * p);
-        out[0] = v4i{tab[0], tab[1], tab[2], tab[3]};
-        out[1] = v4i{tab[4], tab[5], tab[6], tab[7]};
-      }
-      if (a.ccc) {
-        int sum = 0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) sum += tab[e];
-        const int m_ijk = sum >> 3;
-        double res[8];
-        if (m_ijk > 0) {
-          const v4i civ = reinterpret_cast<const v4i*>(a.counts)[i];
-          const v4i ckv = reinterpret_cast<const v4i*>(a.counts)[k];
-          const double wi[2] = {one_minus_gf(civ.x, civ.z, a.gamma),
-                                one_minus_gf(civ.y, civ.z, a.gamma)};
-          const double wk[2] = {one_minus_gf(ckv.x, ckv.z, a.gamma),
-                                one_minus_gf(ckv.y, ckv.z, a.gamma)};
-          const double den = 8.0 * (double)m_ijk;
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            res[e] = ((double)tab[e] / den) * wi[e >> 2] * wj[(e >> 1) & 1] * wk[e & 1];
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) res[e] = 0.0;
-        }
-        double2* out = reinterpret_cast<double2*>(a.ccc + 8 * p);
-        out[0] = double2{res[0], res[1]};
-        out[1] = double2{res[2], res[3]};
-        out[2] = double2{res[4], res[5]};
-        out[3] = double2{res[6], res[7]};
-      }
+      emit_triple(a, kvalid && i < j, i, j, k, tab, wj, wk);
     }
   }
 }

@@ -9,6 +9,43 @@
 namespace ccc {
 namespace tile2 {
 
+// Output of one pair (i, j) with table t (Eqs. (2)-(3)).  Dense mode stores
+// the table and/or CCC at entry p(i,j) - p_base (adding the old table first
+// when accumulating); selection mode keeps the pair only if one of its CCC
+// values reaches the threshold.  In selection mode every lane of the wave
+// must call it (the slot is taken with one atomic per wave); `valid` says
+// whether this lane holds a pair to emit.
+__device__ __forceinline__ void emit_pair(const Pair2Args& a, bool valid, int64_t i, int64_t j,
+                                          v4i t) {
+  valid = valid && i >= a.row_begin && i < a.row_end;
+  if (a.sel.count) {
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    bool keep = false;
+    int64_t p = 0;
+    if (valid) {
+      p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
+      pair_ccc(t, reinterpret_cast<const v4i*>(a.counts_a)[i],
+               reinterpret_cast<const v4i*>(a.counts_b)[j], a.gamma, r);
+      keep = r[0] >= a.sel.threshold || r[1] >= a.sel.threshold ||
+             r[2] >= a.sel.threshold || r[3] >= a.sel.threshold;
+    }
+    const int64_t slot = select_slot(keep, a.sel.count);
+    if (slot >= 0 && slot < a.sel.cap) {
+      a.sel.index[slot] = p;
+      double2* c = reinterpret_cast<double2*>(a.sel.ccc + 4 * slot);
+      c[0] = double2{r[0], r[1]};
+      c[1] = double2{r[2], r[3]};
+      if (a.sel.tables) *reinterpret_cast<v4i*>(a.sel.tables + 4 * slot) = t;
+    }
+    return;
+  }
+  if (!valid) return;
+  const int64_t p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
+  if (a.accumulate) t = t + *reinterpret_cast<const v4i*>(a.tables + 4 * p);
+  store_pair(p - a.p_base, t, reinterpret_cast<const v4i*>(a.counts_a)[i],
+             reinterpret_cast<const v4i*>(a.counts_b)[j], a.gamma, a.tables, a.ccc);
+}
+
 // ---------------------------------------------------------------------------
 // int8-MFMA path
 //
@@ -156,13 +193,9 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
       for (int e = 0; e < 4; ++e) {
         const int64_t i = row0 + 16 * m + 4 * g + e;
         const int64_t j = col0 + 16 * n + rl;
-        if (i >= a.n_a || j >= a.n_b || (a.tri && i >= j)) continue;
-        v4i t = v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]};
-        int64_t p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
-        if (a.accumulate) t = t + *reinterpret_cast<const v4i*>(a.tables + 4 * p);
-        v4i ci = reinterpret_cast<const v4i*>(a.counts_a)[i];
-        v4i cj = reinterpret_cast<const v4i*>(a.counts_b)[j];
-        store_pair(p, t, ci, cj, a.gamma, a.tables, a.ccc);
+        const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
+        emit_pair(a, valid, i, j,
+                  v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]});
       }
 }
 
@@ -287,18 +320,11 @@ __device__ __forceinline__ void pop2_block_tile(const Pair2Args& a, int64_t I, i
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t j = J0 + tx + 16 * c;
-      if (i >= a.n_a || j >= a.n_b || (a.tri && i >= j)) continue;
+      const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
       int x11 = (int)c11[r][c], x1p = (int)s1p[r][c], xp1 = (int)sp1[r][c],
           xpp = (int)spp[r][c];
-      v4i t = v4i{4 * xpp - 2 * xp1 - 2 * x1p + x11, 2 * xp1 - x11, 2 * x1p - x11, x11};
-      int64_t p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
-      if (a.accumulate) {
-        v4i o = *reinterpret_cast<const v4i*>(a.tables + 4 * p);
-        t = t + o;
-      }
-      v4i ci = reinterpret_cast<const v4i*>(a.counts_a)[i];
-      v4i cj = reinterpret_cast<const v4i*>(a.counts_b)[j];
-      store_pair(p, t, ci, cj, a.gamma, a.tables, a.ccc);
+      emit_pair(a, valid, i, j,
+                v4i{4 * xpp - 2 * xp1 - 2 * x1p + x11, 2 * xp1 - x11, 2 * x1p - x11, x11});
     }
   }
 }

@@ -1,0 +1,89 @@
+// tile3.h -- output of one 3-way triple (Sec. 2.2, Eqs. (4)-(5)), shared by
+// the MFMA and popcount 3-way kernels.
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ccc {
+
+// CCC of one triple from its table t (entry 4a+2b+c) and the per-vector
+// factors w_x[a] = 1 - gamma f_x(a); all zero when m_ijk = 0.
+__device__ __forceinline__ void triple_ccc(const int (&t)[8], const double (&wi)[2],
+                                           const double (&wj)[2], const double (&wk)[2],
+                                           double (&r)[8]) {
+#pragma clang fp contract(off)
+  int sum = 0;
+#pragma unroll
+  for (int x = 0; x < 8; ++x) sum += t[x];
+  const int m_ijk = sum >> 3;  // fields where all three are present
+  if (m_ijk > 0) {
+    const double den = 8.0 * (double)m_ijk;
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+      r[x] = ((double)t[x] / den) * wi[x >> 2] * wj[(x >> 1) & 1] * wk[x & 1];
+  } else {
+#pragma unroll
+    for (int x = 0; x < 8; ++x) r[x] = 0.0;
+  }
+}
+
+__device__ __forceinline__ void vector_factors(const int32_t* __restrict__ counts, int64_t x,
+                                               double gamma, double (&w)[2]) {
+  const v4i c = reinterpret_cast<const v4i*>(counts)[x];
+  w[0] = one_minus_gf(c.x, c.z, gamma);
+  w[1] = one_minus_gf(c.y, c.z, gamma);
+}
+
+// Dense mode: table and/or CCC at entry T(i,j,k) - t_base.  Selection mode:
+// keep the triple if one of its CCC values reaches the threshold; then every
+// lane of the wave must call (one atomic per wave) and `valid` marks lanes
+// that hold a triple.  wj / wk are the factors of j and k (valid lanes only).
+__device__ __forceinline__ void emit_triple(const Triple3Args& a, bool valid, int64_t i,
+                                            int64_t j, int64_t k, const int (&t)[8],
+                                            const double (&wj)[2], const double (&wk)[2]) {
+  valid = valid && i >= a.i_begin && i < a.i_end;
+  if (a.sel.count) {
+    double r[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool keep = false;
+    int64_t p = 0;
+    if (valid) {
+      p = triple_index(a.n, i, j, k);
+      double wi[2];
+      vector_factors(a.counts, i, a.gamma, wi);
+      triple_ccc(t, wi, wj, wk, r);
+#pragma unroll
+      for (int x = 0; x < 8; ++x) keep = keep || r[x] >= a.sel.threshold;
+    }
+    const int64_t slot = select_slot(keep, a.sel.count);
+    if (slot >= 0 && slot < a.sel.cap) {
+      a.sel.index[slot] = p;
+      double2* c = reinterpret_cast<double2*>(a.sel.ccc + 8 * slot);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) c[x] = double2{r[2 * x], r[2 * x + 1]};
+      if (a.sel.tables) {
+        v4i* o = reinterpret_cast<v4i*>(a.sel.tables + 8 * slot);
+        o[0] = v4i{t[0], t[1], t[2], t[3]};
+        o[1] = v4i{t[4], t[5], t[6], t[7]};
+      }
+    }
+    return;
+  }
+  if (!valid) return;
+  const int64_t p = triple_index(a.n, i, j, k) - a.t_base;
+  if (a.tables) {
+    v4i* o = reinterpret_cast<v4i*>(a.tables + 8 * p);
+    o[0] = v4i{t[0], t[1], t[2], t[3]};
+    o[1] = v4i{t[4], t[5], t[6], t[7]};
+  }
+  if (a.ccc) {
+    double wi[2], r[8];
+    vector_factors(a.counts, i, a.gamma, wi);
+    triple_ccc(t, wi, wj, wk, r);
+    double2* c = reinterpret_cast<double2*>(a.ccc + 8 * p);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) c[x] = double2{r[2 * x], r[2 * x + 1]};
+  }
+}
+
+}  // namespace ccc

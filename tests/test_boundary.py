@@ -117,3 +117,40 @@ def test_many_validation_checks_every_problem():
         assert L.ccc_2way_many(arr, 3, None, None) == want
     assert L.ccc_2way_many(None, 2, None, None) == ccc.CCC_ERR_ARG
     assert L.ccc_2way_many(None, -1, None, None) == ccc.CCC_ERR_ARG
+
+
+def test_rows_and_select_validation():
+    L = ccc.lib()
+    o = ctypes.byref(ccc.make_opts())
+    for fn in (L.ccc_2way_rows, L.ccc_3way_rows):
+        assert fn(FAKE, 10, 100, 32, -1, 5, FAKE, FAKE, None, o, None) == ccc.CCC_ERR_ARG
+        assert fn(FAKE, 10, 100, 32, 6, 5, FAKE, FAKE, None, o, None) == ccc.CCC_ERR_ARG
+        assert fn(FAKE, 10, 100, 32, 0, 11, FAKE, FAKE, None, o, None) == ccc.CCC_ERR_ARG
+        assert fn(FAKE, 10, 100, 32, 0, 5, None, None, None, o, None) == ccc.CCC_ERR_ARG
+        assert fn(FAKE, 10, 100, 24, 0, 5, FAKE, FAKE, None, o, None) == ccc.CCC_ERR_ALIGN
+        # an empty range needs no outputs and does no work
+        assert fn(FAKE, 0, 100, 32, 0, 0, None, None, None, o, None) == ccc.CCC_OK
+    S = ccc.ccc_selection
+    good = S(FAKE, FAKE, FAKE, 10, FAKE)
+    for fn in (L.ccc_2way_select, L.ccc_3way_select):
+        assert fn(FAKE, 10, 100, 32, 0.1, None, None, o, None) == ccc.CCC_ERR_ARG
+        assert fn(FAKE, 10, 100, 32, float("nan"), ctypes.byref(good), None, o,
+                  None) == ccc.CCC_ERR_ARG
+        for bad in (S(None, FAKE, FAKE, 10, FAKE), S(FAKE, None, FAKE, 10, FAKE),
+                    S(FAKE, FAKE, FAKE, 10, None), S(FAKE, FAKE, FAKE, -1, FAKE)):
+            assert fn(FAKE, 10, 100, 32, 0.1, ctypes.byref(bad), None, o, None) == ccc.CCC_ERR_ARG
+        for bad in (S(FAKE + 8, FAKE, FAKE, 10, FAKE), S(FAKE, FAKE, FAKE + 4, 10, FAKE),
+                    S(FAKE, FAKE, FAKE, 10, FAKE + 8)):
+            assert fn(FAKE, 10, 100, 32, 0.1, ctypes.byref(bad), None, o,
+                      None) == ccc.CCC_ERR_ALIGN
+        assert fn(FAKE, 0, 100, 32, 0.1, ctypes.byref(good), None, o, None) == ccc.CCC_OK
+
+
+def test_ranges_without_pairs_need_no_outputs():
+    L = ccc.lib()
+    o = ctypes.byref(ccc.make_opts())
+    # the last row has no pair, the last two rows no triple: no outputs needed,
+    # and with no counts requested nothing is launched
+    assert L.ccc_2way_rows(FAKE, 10, 100, 32, 9, 10, None, None, None, o, None) == ccc.CCC_OK
+    assert L.ccc_3way_rows(FAKE, 10, 100, 32, 8, 10, None, None, None, o, None) == ccc.CCC_OK
+    assert L.ccc_2way_rows(FAKE, 10, 100, 32, 8, 10, None, None, None, o, None) == ccc.CCC_ERR_ARG
