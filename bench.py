@@ -155,6 +155,19 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
                                traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                                algorithmic_bytes=n_v * ((n_f + 3) // 4) + 48 * P + 32 * n_v,
                                kernel="mfma2_kernel", kernel_ms=kms)
+        if args.select_threshold is not None:
+            thr = args.select_threshold
+            log(f"timing threshold selection at {thr}")
+            found = {}
+
+            def sel_step():
+                found["n"] = ccc.ccc_2way_select(dv, n_f, thr, cap=1 << 22, counts=counts)[0]
+
+            sms, _, _ = timed(sel_step, args.steps, 1, lib, "mfma2")
+            out["select"] = dict(threshold=thr, kept=found["n"], ms_per_step=sms,
+                                 value=comps / (sms / 1e3),
+                                 note="ccc_2way_select: only pairs with a CCC value >= "
+                                      "threshold are written (includes a count read-back)")
         if args.pop_steps > 0:
             log(f"timing popcount: 1 warmup + {args.pop_steps} steps")
             pms, pkms, _ = timed(lambda: step("popcount"), args.pop_steps, 1, lib, "pop2")
@@ -202,6 +215,18 @@ def bench_3way(args, lib):
                              traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                              algorithmic_bytes=n_v * ((n_f + 3) // 4) + 96 * T + 16 * n_v,
                              kernel="mfma3_kernel", kernel_ms=kms))
+    if args.select_threshold is not None:
+        thr = args.select_threshold
+        found = {}
+
+        def sel_step():
+            found["n"] = ccc.ccc_3way_select(dv, n_f, thr, cap=1 << 22, counts=counts)[0]
+
+        sms, _, _ = timed(sel_step, args.steps, 1, lib, "mfma3")
+        out["select"] = dict(threshold=thr, kept=found["n"], ms_per_step=sms,
+                             value=comps / (sms / 1e3),
+                             note="ccc_3way_select: only triples with a CCC value >= threshold "
+                                  "are written (includes a count read-back)")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_3way(v, n_f, 1)
     return out
@@ -283,6 +308,10 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--select-threshold", type=float, default=None,
+                    help="also time the threshold-filtered entry point (c2, c3); e.g. 0.13 "
+                         "for 2-way, 0.05 for 3-way (independent vectors stay below 0.141 and "
+                         "0.053)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain elementwise copy of 1 GiB (read 1 GiB, write 1 GiB) "
                          "to scale the HBM byte counters")
