@@ -11,7 +11,8 @@ allele frequency ~ Beta(1/2,1/2), Hardy-Weinberg genotypes, 1% missing) on
 the int8-MFMA path; the popcount path is timed on the same input for the
 ratio.  Prints one JSON line.
 
-Other workloads (--config): c1 (2-way 512 x 1000, popcount path), c3 (3-way
+Other workloads (--config): c1 (2-way 512 x 1000, popcount path), c2c (the
+c2 shape with no missing entries: the complete-data path), c3 (3-way
 2048 x 16384), c4 (64 batched 2-way problems), c5 (2-way off-diagonal block
 16384 x 16384 over 131072 fields in 8 chunks).
 """
@@ -144,7 +145,9 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
                dtype="i8" if path == "mfma" else "u32", data="synthetic",
                config=dict(workload=workload, n_v=n_v, n_f=n_f, missing=missing, path=path))
     if path == "mfma":
-        ops = 8.0 * comps  # 4 int8 MACs per comparison
+        # 4 int8 MACs per comparison; with no missing entry anywhere every tile
+        # takes the one-plane complete-data form (1 MAC per comparison)
+        ops = (2.0 if missing == 0.0 else 8.0) * comps
         ach = ops / (kms / 1e3) / 1e12
         traffic = None
         if (n_v, n_f) == (32768, 65536):
@@ -154,7 +157,8 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
                                frac=ach / INT8_PEAK_TOPS, traffic=traffic,
                                traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                                algorithmic_bytes=n_v * ((n_f + 3) // 4) + 48 * P + 32 * n_v,
-                               kernel="mfma2_kernel", kernel_ms=kms)
+                               kernel="mfma2_kernel", kernel_ms=kms,
+                               int8_ops_per_comparison=2 if missing == 0.0 else 8)
         if args.select_threshold is not None:
             thr = args.select_threshold
             log(f"timing threshold selection at {thr}")
@@ -305,7 +309,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pop-steps", type=int, default=2, help="popcount-path steps (c2)")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c2c", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=8)
     ap.add_argument("--select-threshold", type=float, default=None,
@@ -339,6 +343,10 @@ def main():
         out = bench_2way(args, lib, 32768, 65536, 0.01, "beta_hw", "mfma",
                          "2-way CCC large: n_v=32768 x n_f=65536, Beta(0.5,0.5)/Hardy-Weinberg, "
                          "1% missing", args.cpu_rows)
+    elif args.config == "c2c":
+        out = bench_2way(args, lib, 32768, 65536, 0.0, "beta_hw", "mfma",
+                         "2-way CCC, complete data: n_v=32768 x n_f=65536, "
+                         "Beta(0.5,0.5)/Hardy-Weinberg, no missing", args.cpu_rows)
     elif args.config == "c1":
         out = bench_2way(args, lib, 512, 1000, 0.0, "uniform", "popcount",
                          "2-way CCC: n_v=512 x n_f=1000, uniform genotypes, no missing", 512)

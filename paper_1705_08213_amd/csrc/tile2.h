@@ -96,6 +96,76 @@ __device__ __forceinline__ unsigned word_of(const u4& x, int s) {
   return s == 0 ? x.x : (s == 1 ? x.y : (s == 2 ? x.z : x.w));
 }
 
+// rho(1) of 16 fields (one packed word), as for unpack16.
+__device__ __forceinline__ v4i unpack16_rho1(unsigned w) {
+  unsigned c0 = w & kLow2, c1 = (w >> 2) & kLow2, c2 = (w >> 4) & kLow2, c3 = (w >> 6) & kLow2;
+  return v4i{(int)__builtin_amdgcn_perm(0u, kRho1Table, c0),
+             (int)__builtin_amdgcn_perm(0u, kRho1Table, c1),
+             (int)__builtin_amdgcn_perm(0u, kRho1Table, c2),
+             (int)__builtin_amdgcn_perm(0u, kRho1Table, c3)};
+}
+
+// Complete-data super-step: only C11 = sum rho_i(1) rho_j(1) (one plane).
+template <int WM, int WN>
+__device__ __forceinline__ void mma_superstep_rho1(const u4 (&pa)[WM], const u4 (&pb)[WN],
+                                                   v4i (&acc)[WM][WN]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    v4i a1[WM], b1[WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m) a1[m] = unpack16_rho1(word_of(pa[m], s));
+#pragma unroll
+    for (int n = 0; n < WN; ++n) b1[n] = unpack16_rho1(word_of(pb[n], s));
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int n = 0; n < WN; ++n)
+        acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1[m], b1[n], acc[m][n], 0, 0, 0);
+  }
+}
+
+// Run the super-step loop of a wave tile: `step` consumes the 16-byte pieces
+// of every row (plain loads while all 256 fields are inside n_f, prefetched
+// one super-step ahead; then one masked tail step).
+template <int WM, int WN, typename Step>
+__device__ __forceinline__ void wave_loop(const uint8_t* const (&pa)[WM],
+                                          const uint8_t* const (&pb)[WN], int g, int64_t n_f,
+                                          Step step) {
+  const int64_t nfull = n_f / 256;
+  const int64_t nbytes = (n_f + 3) / 4;
+  u4 ca[WM], cb[WN];
+  if (nfull > 0) {
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = *reinterpret_cast<const u4*>(pa[m]);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = *reinterpret_cast<const u4*>(pb[n]);
+  }
+  for (int64_t s = 0; s < nfull; ++s) {
+    u4 na[WM], nb[WN];
+    const int64_t kn = (s + 1) * 64;
+    if (s + 1 < nfull) {
+#pragma unroll
+      for (int m = 0; m < WM; ++m) na[m] = *reinterpret_cast<const u4*>(pa[m] + kn);
+#pragma unroll
+      for (int n = 0; n < WN; ++n) nb[n] = *reinterpret_cast<const u4*>(pb[n] + kn);
+    }
+    step(ca, cb);
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = na[m];
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = nb[n];
+  }
+  const int64_t kt = nfull * 64;
+  if (kt < nbytes) {
+    // row pointers already include the lane's 16*g byte offset
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = load_fields64(pa[m] - 16 * g, kt + 16 * g, n_f);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = load_fields64(pb[n] - 16 * g, kt + 16 * g, n_f);
+    step(ca, cb);
+  }
+}
+
 template <int WM, int WN>
 __device__ __forceinline__ void mma_superstep(const u4 (&pa)[WM], const u4 (&pb)[WN],
                                               v4i (&acc)[WM][WN][4]) {
@@ -140,6 +210,54 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     pb[n] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
   }
 
+  // Complete data (every row of this wave tile has all n_f fields present,
+  // as the 1-way counts of this call say): P = 1, so the table follows from
+  // C11 = sum rho_i(1) rho_j(1) and the allele counts n(1):
+  //   C10 = 2 n_i(1) - C11,  C01 = 2 n_j(1) - C11,
+  //   C00 = 4 n_f - 2 n_i(1) - 2 n_j(1) + C11,
+  // one MFMA plane instead of four.  The vote is wave-uniform.
+  bool mine = !a.accumulate && a.n_f > 0;
+#pragma unroll
+  for (int m = 0; m < WM; ++m) {
+    int64_t r = row0 + 16 * m + rl;
+    r = r < a.n_a ? r : a.n_a - 1;
+    mine = mine && reinterpret_cast<const v4i*>(a.counts_a)[r].z == a.n_f;
+  }
+#pragma unroll
+  for (int n = 0; n < WN; ++n) {
+    int64_t r = col0 + 16 * n + rl;
+    r = r < a.n_b ? r : a.n_b - 1;
+    mine = mine && reinterpret_cast<const v4i*>(a.counts_b)[r].z == a.n_f;
+  }
+  if (__all(mine ? 1 : 0)) {
+    v4i acc1[WM][WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int n = 0; n < WN; ++n) acc1[m][n] = v4i{0, 0, 0, 0};
+    wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
+      mma_superstep_rho1<WM, WN>(ca, cb, acc1);
+    });
+    const int nf4 = (int)(4 * a.n_f);
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int n = 0; n < WN; ++n) {
+        const int64_t j = col0 + 16 * n + rl;
+        const int n1j = reinterpret_cast<const v4i*>(a.counts_b)[j < a.n_b ? j : a.n_b - 1].y;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t i = row0 + 16 * m + 4 * g + e;
+          const int n1i = reinterpret_cast<const v4i*>(a.counts_a)[i < a.n_a ? i : a.n_a - 1].y;
+          const int c11 = acc1[m][n][e];
+          const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
+          emit_pair(a, valid, i, j,
+                    v4i{nf4 - 2 * n1i - 2 * n1j + c11, 2 * n1j - c11, 2 * n1i - c11, c11});
+        }
+      }
+    return;
+  }
+
   v4i acc[WM][WN][4];
 #pragma unroll
   for (int m = 0; m < WM; ++m)
@@ -147,42 +265,9 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     for (int n = 0; n < WN; ++n)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[m][n][e] = v4i{0, 0, 0, 0};
-
-  // Super-steps of 256 fields (64 bytes per row).  The first nfull are
-  // entirely inside n_f (so inside the row stride); one masked step follows.
-  const int64_t nfull = a.n_f / 256;
-  const int64_t nbytes = (a.n_f + 3) / 4;
-  u4 ca[WM], cb[WN];
-  if (nfull > 0) {
-#pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = *reinterpret_cast<const u4*>(pa[m]);
-#pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = *reinterpret_cast<const u4*>(pb[n]);
-  }
-  for (int64_t s = 0; s < nfull; ++s) {
-    u4 na[WM], nb[WN];
-    const int64_t kn = (s + 1) * 64;
-    if (s + 1 < nfull) {
-#pragma unroll
-      for (int m = 0; m < WM; ++m) na[m] = *reinterpret_cast<const u4*>(pa[m] + kn);
-#pragma unroll
-      for (int n = 0; n < WN; ++n) nb[n] = *reinterpret_cast<const u4*>(pb[n] + kn);
-    }
+  wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
     mma_superstep<WM, WN>(ca, cb, acc);
-#pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = na[m];
-#pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = nb[n];
-  }
-  const int64_t kt = nfull * 64;
-  if (kt < nbytes) {
-    // row pointers already include the lane's 16*g byte offset
-#pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = load_fields64(pa[m] - 16 * g, kt + 16 * g, a.n_f);
-#pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = load_fields64(pb[n] - 16 * g, kt + 16 * g, a.n_f);
-    mma_superstep<WM, WN>(ca, cb, acc);
-  }
+  });
 
   // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
 #pragma unroll
@@ -248,9 +333,12 @@ struct Pop2Smem {
 };
 
 // The 64 x 64 tile (I, J) of pairs for the whole workgroup (256 threads; every
-// thread must call it, it uses workgroup barriers).
-__device__ __forceinline__ void pop2_block_tile(const Pair2Args& a, int64_t I, int64_t J,
-                                                Pop2Smem& sm) {
+// thread must call it, it uses workgroup barriers).  COMPLETE: every row of
+// the tile has all n_f fields present, so P = 1 and only c11 is counted
+// (4 AND + bit counts per 32 fields); s1p = n_i(1), sp1 = n_j(1), spp = n_f.
+template <bool COMPLETE>
+__device__ __forceinline__ void pop2_tile_body(const Pair2Args& a, int64_t I, int64_t J,
+                                               Pop2Smem& sm) {
   const int64_t I0 = I * kTile, J0 = J * kTile;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
 
@@ -307,9 +395,11 @@ __device__ __forceinline__ void pop2_block_tile(const Pair2Args& a, int64_t I, i
           x += __popc(aH[r] & bO[c]);
           x += __popc(aH[r] & bH[c]);
           c11[r][c] = x;
-          s1p[r][c] += __popc(aO[r] & bP[c]) + __popc(aH[r] & bP[c]);
-          sp1[r][c] += __popc(aP[r] & bO[c]) + __popc(aP[r] & bH[c]);
-          spp[r][c] += __popc(aP[r] & bP[c]);
+          if (!COMPLETE) {
+            s1p[r][c] += __popc(aO[r] & bP[c]) + __popc(aH[r] & bP[c]);
+            sp1[r][c] += __popc(aP[r] & bO[c]) + __popc(aP[r] & bH[c]);
+            spp[r][c] += __popc(aP[r] & bP[c]);
+          }
         }
     }
   }
@@ -323,10 +413,37 @@ __device__ __forceinline__ void pop2_block_tile(const Pair2Args& a, int64_t I, i
       const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
       int x11 = (int)c11[r][c], x1p = (int)s1p[r][c], xp1 = (int)sp1[r][c],
           xpp = (int)spp[r][c];
+      if (COMPLETE) {
+        x1p = reinterpret_cast<const v4i*>(a.counts_a)[i < a.n_a ? i : a.n_a - 1].y;
+        xp1 = reinterpret_cast<const v4i*>(a.counts_b)[j < a.n_b ? j : a.n_b - 1].y;
+        xpp = (int)a.n_f;
+      }
       emit_pair(a, valid, i, j,
                 v4i{4 * xpp - 2 * xp1 - 2 * x1p + x11, 2 * xp1 - x11, 2 * x1p - x11, x11});
     }
   }
+}
+
+
+__device__ __forceinline__ void pop2_block_tile(const Pair2Args& a, int64_t I, int64_t J,
+                                                Pop2Smem& sm) {
+  // workgroup-uniform vote: each thread checks the row it stages
+  const int tid = threadIdx.x;
+  const int side = tid >> 7, lrow = (tid >> 1) & 63;
+  int mine = !a.accumulate && a.n_f > 0;
+  if (side == 0) {
+    int64_t r = I * kTile + lrow;
+    r = r < a.n_a ? r : a.n_a - 1;
+    mine = mine && reinterpret_cast<const v4i*>(a.counts_a)[r].z == a.n_f;
+  } else {
+    int64_t r = J * kTile + lrow;
+    r = r < a.n_b ? r : a.n_b - 1;
+    mine = mine && reinterpret_cast<const v4i*>(a.counts_b)[r].z == a.n_f;
+  }
+  if (__syncthreads_and(mine))
+    pop2_tile_body<true>(a, I, J, sm);
+  else
+    pop2_tile_body<false>(a, I, J, sm);
 }
 
 }  // namespace tile2

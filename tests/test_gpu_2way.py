@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.brute
 import paper_1705_08213_amd as ccc
 import synth
 from gpu_util import assert_ccc_close, assert_tables_equal, dev, host, say
@@ -108,3 +109,24 @@ def test_2way_paths_agree_and_are_deterministic():
         lo = oracle.pair_index(1000, i0, i0 + 1)
         assert_tables_equal(tm[lo:lo + len(ot)], ot)
         assert_ccc_close(cm[lo:lo + len(ot)], oc)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n_v,n_f", [(200, 3001), (300, 512), (70, 9)])
+def test_2way_complete_data_and_single_missing_entry(path, n_v, n_f):
+    """Complete inputs take the one-plane path on the MFMA side; one missing
+    entry in one row sends only the tiles holding that row to the general
+    path.  Both must match the oracle."""
+    say("2way complete", path, n_v, n_f)
+    v = synth.beta_hw(n_v, n_f, seed=77 + n_v, missing=0.0)
+    t, c, _ = run2(v, n_f, path)
+    ot, oc = oracle.two_way(v, n_f)
+    assert_tables_equal(t, ot)
+    assert_ccc_close(c, oc)
+    codes = oracle.brute.unpack_codes(v, n_f)
+    codes[n_v // 2, n_f // 3] = 2  # one missing entry
+    v2 = synth.pack_codes(codes, pad_value=-1)
+    t2, c2, _ = run2(v2, n_f, path)
+    ot2, oc2 = oracle.two_way(v2, n_f)
+    assert_tables_equal(t2, ot2)
+    assert_ccc_close(c2, oc2)

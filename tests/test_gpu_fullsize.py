@@ -187,3 +187,28 @@ def test_c4_batched_full_size():
         t1, c1, _ = ccc.ccc_2way(probs[k]["v"], probs[k]["n_f"])
         sync()
         assert torch.equal(t1, outs[k][0]) and torch.equal(c1, outs[k][1])
+
+
+def test_c2_shape_complete_data_full_size():
+    """The large 2-way shape with no missing entries (the paper's main-text
+    setting): every tile takes the one-plane MFMA path."""
+    import torch
+    n_v, n_f = 32768, 65536
+    say("c2 complete: generate")
+    v = synth.beta_hw(n_v, n_f, seed=0, missing=0.0)
+    dv = dev(v)
+    say("c2 complete: mfma")
+    t, c, cnt = ccc.ccc_2way(dv, n_f, path="mfma")
+    sync()
+    assert int(cnt[:, 2].min()) == n_f
+    rng = np.random.default_rng(12)
+    ia, jb = sample_pairs(n_v, rng, count=1000)
+    ot, oc = oracle.pairs_list(v, v, n_f, ia, jb)
+    p = pair_index_np(n_v, ia, jb)
+    assert_tables_equal(gather_rows(t, p), ot)
+    assert_ccc_close(gather_rows(c, p), oc)
+    del c
+    say("c2 complete: checksum")
+    w, u = synth.weights(n_v, seed=9, tag=0), synth.weights(n_v, seed=9, tag=1)
+    assert np.array_equal(oracle.fp2_from_tables(t.cpu().numpy(), n_v, w, u),
+                          oracle.fp2_from_input(v, n_f, w, u))
