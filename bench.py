@@ -13,8 +13,9 @@ ratio.  Prints one JSON line.
 
 Other workloads (--config): c1 (2-way 512 x 1000, popcount path), c2c (the
 c2 shape with no missing entries: the complete-data path), c3 (3-way
-2048 x 16384), c4 (64 batched 2-way problems), c5 (2-way off-diagonal block
-16384 x 16384 over 131072 fields in 8 chunks).
+2048 x 16384), c3c (the c3 shape with no missing entries), c4 (64 batched
+2-way problems), c5 (2-way off-diagonal block 16384 x 16384 over 131072
+fields in 8 chunks).
 """
 from __future__ import annotations
 
@@ -55,8 +56,10 @@ def committed_traffic(kernel_sources, profile):
 
 
 MFMA2_SOURCES = ["paper_1705_08213_amd/csrc/mfma2.hip", "paper_1705_08213_amd/csrc/tile2.h",
-                 "paper_1705_08213_amd/csrc/common.h"]
-MFMA3_SOURCES = ["paper_1705_08213_amd/csrc/mfma3.hip", "paper_1705_08213_amd/csrc/common.h"]
+                 "paper_1705_08213_amd/csrc/common.h", "paper_1705_08213_amd/csrc/kernels.h"]
+MFMA3_SOURCES = ["paper_1705_08213_amd/csrc/mfma3.hip", "paper_1705_08213_amd/csrc/tile3.h",
+                 "paper_1705_08213_amd/csrc/tile2.h", "paper_1705_08213_amd/csrc/common.h",
+                 "paper_1705_08213_amd/csrc/kernels.h"]
 
 
 def timing_query(lib, name):
@@ -187,11 +190,11 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
     return out
 
 
-def bench_3way(args, lib):
+def bench_3way(args, lib, missing, workload):
     import torch
     import paper_1705_08213_amd as ccc
     import synth
-    n_v, n_f, missing = 2048, 16384, 0.005
+    n_v, n_f = 2048, 16384
     log(f"generating {n_v} x {n_f} input")
     v = synth.beta_hw(n_v, n_f, seed=0, missing=missing)
     dv = torch.from_numpy(v).cuda()
@@ -205,20 +208,30 @@ def bench_3way(args, lib):
 
     ms, kms, _ = timed(step, args.steps, args.warmup, lib, "mfma3")
     comps = T * n_f
-    ach = 16.0 * comps / (kms / 1e3) / 1e12
+    # 8 int8 MACs per comparison; with no missing entry every unit takes the
+    # one-plane complete-data form (1 MAC per comparison)
+    ops_per = 2.0 if missing == 0.0 else 16.0
+    ach = ops_per * comps / (kms / 1e3) / 1e12
+    alg_bytes = n_v * ((n_f + 3) // 4) + 96 * T + 16 * n_v
+    roof = dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
+                frac=ach / INT8_PEAK_TOPS, traffic=None,
+                traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
+                algorithmic_bytes=alg_bytes, kernel="mfma3_kernel", kernel_ms=kms,
+                int8_ops_per_comparison=int(ops_per))
+    roof["traffic"] = committed_traffic(
+        MFMA3_SOURCES, "profiles/mfma3_3way_n2048_f16384.md" if missing > 0.0
+        else "profiles/mfma3_3way_complete_n2048_f16384.md")
+    hbm = alg_bytes / (kms / 1e3) / 1e9
+    if hbm / HBM_PEAK_GBS > roof["frac"]:
+        # the output stream, not the matrix cores, is the nearer ceiling
+        roof.update(bound="hbm", achieved=hbm, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=hbm / HBM_PEAK_GBS, mfma_frac=ach / INT8_PEAK_TOPS)
     out = dict(metric="CCC comparisons/sec (triples*n_f), bit-exact tables",
                value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="i8", data="synthetic",
-               config=dict(workload="3-way CCC: n_v=2048 x n_f=16384, Beta/HW, 0.5% missing",
-                           n_v=n_v, n_f=n_f, missing=missing, path="mfma"),
-               roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                             frac=ach / INT8_PEAK_TOPS,
-                             traffic=committed_traffic(MFMA3_SOURCES,
-                                                       "profiles/mfma3_3way_n2048_f16384.md"),
-                             traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
-                             algorithmic_bytes=n_v * ((n_f + 3) // 4) + 96 * T + 16 * n_v,
-                             kernel="mfma3_kernel", kernel_ms=kms))
+               config=dict(workload=workload, n_v=n_v, n_f=n_f, missing=missing, path="mfma"),
+               roofline=roof)
     if args.select_threshold is not None:
         thr = args.select_threshold
         found = {}
@@ -309,7 +322,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pop-steps", type=int, default=2, help="popcount-path steps (c2)")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c2c", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2",
+                    choices=["c1", "c2", "c2c", "c3", "c3c", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=8)
     ap.add_argument("--select-threshold", type=float, default=None,
@@ -351,7 +365,11 @@ def main():
         out = bench_2way(args, lib, 512, 1000, 0.0, "uniform", "popcount",
                          "2-way CCC: n_v=512 x n_f=1000, uniform genotypes, no missing", 512)
     elif args.config == "c3":
-        out = bench_3way(args, lib)
+        out = bench_3way(args, lib, 0.005, "3-way CCC: n_v=2048 x n_f=16384, "
+                                           "Beta(0.5,0.5)/Hardy-Weinberg, 0.5% missing")
+    elif args.config == "c3c":
+        out = bench_3way(args, lib, 0.0, "3-way CCC, complete data: n_v=2048 x n_f=16384, "
+                                         "Beta(0.5,0.5)/Hardy-Weinberg, no missing")
     elif args.config == "c4":
         out = bench_many(args, lib)
     else:

@@ -17,6 +17,10 @@
 namespace {
 
 constexpr int64_t kInt32Max = 2147483647;
+// Largest row count whose complete-data Gram matrix (4 B per entry) the
+// 3-way MFMA path keeps in the workspace (4 GiB); beyond it every unit takes
+// the general path.
+constexpr int64_t kGramMaxRows = 32768;
 
 struct Workspace {
   void* ptr = nullptr;
@@ -207,10 +211,18 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   unsigned long long* zero = sel ? sel->count : nullptr;
   const int64_t row_end = i_end < n_v - 2 ? i_end : n_v - 2;  // first index below n_v - 2
   if (row_end <= i_begin && !counts && !zero) return CCC_OK;  // nothing to compute or write
-  // workspace: offsets of the tetrahedral work units, then (if needed) counts
-  const size_t offs_bytes = ((size_t)(n_v + 1) * 8 + 255) / 256 * 256;
+  // workspace: offsets of the tetrahedral work units (per tile pair), then
+  // (if needed) counts, then (MFMA path) the rho(1) Gram matrix of rows
+  // [g0, n_v) used by complete-data units; g0 is i_begin rounded down to the
+  // unit tile
+  const ccc::UnitGrid ug = ccc::unit_grid(n_v, ccc::kUnitTile, i_begin, row_end);
+  const size_t offs_bytes = ((size_t)(ccc::grid_pairs(ug) + 1) * 8 + 255) / 256 * 256;
+  const size_t cnt_bytes = counts ? 0 : ((size_t)n_v * 16 + 255) / 256 * 256;
+  const int64_t g0 = i_begin / ccc::kUnitTile * ccc::kUnitTile, ng = n_v - g0;
+  const bool use_gram = o.path != CCC_PATH_POPCOUNT && ng <= kGramMaxRows && i_begin < row_end;
+  const size_t gram_bytes = use_gram ? (size_t)ng * (size_t)ng * 4 : 0;
   void* ws = nullptr;
-  if ((st = ccc::workspace(offs_bytes + (counts ? 0 : (size_t)n_v * 16), &ws))) return st;
+  if ((st = ccc::workspace(offs_bytes + cnt_bytes + gram_bytes, &ws))) return st;
   int32_t* cnt = counts ? counts : reinterpret_cast<int32_t*>(static_cast<char*>(ws) + offs_bytes);
   if (n_v < 3)
     return ccc::launch_count1_zero(v, ld, n_v, n_f, cnt, 0, zero, stream) == hipSuccess
@@ -231,6 +243,10 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   a.t_base = choose3(n_v) - choose3(n_v - i_begin);  // T(i_begin, i_begin+1, i_begin+2)
   a.sel = sel ? ccc::Select{sel->count, sel->cap, threshold, sel->index, sel->ccc, sel->tables}
               : ccc::Select{nullptr, 0, 0.0, nullptr, nullptr, nullptr};
+  a.gram = use_gram ? reinterpret_cast<int32_t*>(static_cast<char*>(ws) + offs_bytes + cnt_bytes)
+                    : nullptr;
+  a.g0 = g0;
+  a.ng = use_gram ? ng : 0;
   hipError_t e = o.path == CCC_PATH_POPCOUNT ? ccc::launch_pop3(a, stream)
                                              : ccc::launch_mfma3(a, stream);
   return e == hipSuccess ? CCC_OK : CCC_ERR_HIP;

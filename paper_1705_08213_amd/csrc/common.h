@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels.h"
+
 namespace ccc {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -78,33 +80,57 @@ __device__ __forceinline__ double one_minus_gf(int n_a, int m, double gamma) {
   return 1.0 - gamma * f;
 }
 
+// Per-vector factors w(a) = 1 - gamma f(a), a = 0, 1, from the counts
+// (n(0), n(1), m, 0) of one vector.
+__device__ __forceinline__ void vector_factors(const int32_t* __restrict__ counts, int64_t x,
+                                               double gamma, double (&w)[2]) {
+  const v4i c = reinterpret_cast<const v4i*>(counts)[x];
+  w[0] = one_minus_gf(c.x, c.z, gamma);
+  w[1] = one_minus_gf(c.y, c.z, gamma);
+}
+
+// t / den rounded to nearest, for integers 0 <= t <= den < 2^34, given
+// y = 1/den from one IEEE division shared by all t over the same den.
+// q0 = t y lies within 2 ulp of x = t/den; the residual t - q0 den is then a
+// multiple of ulp(q0) smaller than 2^36 ulp(q0), so one fma gets it exactly; and
+// q0 + residual * y is within 2^-52 ulp of x.  A quotient of such integers is
+// either representable (its reduced denominator is a power of two and its
+// numerator has at most 34 bits) or at least 2^-35 ulp away from every
+// rounding midpoint, so the final rounding gives exactly RN(t/den): the same
+// double as the division itself.
+__device__ __forceinline__ double quot_rn(double t, double den, double y) {
+#pragma clang fp contract(off)
+  const double q0 = t * y;
+  const double r = __builtin_fma(-q0, den, t);
+  return __builtin_fma(r, y, q0);
+}
+
 // CCC of one pair (Eqs. (2)-(3)) from its table t = (C00, C01, C10, C11) and
-// the counts (n(0), n(1), m, 0) of the two vectors; all zero when m_ij = 0.
-__device__ __forceinline__ void pair_ccc(v4i t, v4i ci, v4i cj, double gamma, double (&r)[4]) {
+// the factors w_i, w_j of its two vectors; all zero when m_ij = 0.
+__device__ __forceinline__ void pair_ccc(v4i t, const double (&wi)[2], const double (&wj)[2],
+                                         double (&r)[4]) {
 #pragma clang fp contract(off)
   int sum = t.x + t.y + t.z + t.w;
   int m_ij = sum >> 2;  // fields where both are present
   if (m_ij > 0) {
-    double den = 4.0 * (double)m_ij;
-    double wi0 = one_minus_gf(ci.x, ci.z, gamma), wi1 = one_minus_gf(ci.y, ci.z, gamma);
-    double wj0 = one_minus_gf(cj.x, cj.z, gamma), wj1 = one_minus_gf(cj.y, cj.z, gamma);
-    r[0] = ((double)t.x / den) * wi0 * wj0;
-    r[1] = ((double)t.y / den) * wi0 * wj1;
-    r[2] = ((double)t.z / den) * wi1 * wj0;
-    r[3] = ((double)t.w / den) * wi1 * wj1;
+    const double den = 4.0 * (double)m_ij, y = 1.0 / den;
+    r[0] = quot_rn((double)t.x, den, y) * wi[0] * wj[0];
+    r[1] = quot_rn((double)t.y, den, y) * wi[0] * wj[1];
+    r[2] = quot_rn((double)t.z, den, y) * wi[1] * wj[0];
+    r[3] = quot_rn((double)t.w, den, y) * wi[1] * wj[1];
   } else {
     r[0] = r[1] = r[2] = r[3] = 0.0;
   }
 }
 
 // Dense 2-way store of entry p: the table (if `tables`) and CCC (if `ccc`).
-__device__ __forceinline__ void store_pair(int64_t p, v4i t, v4i ci, v4i cj, double gamma,
-                                           int32_t* __restrict__ tables,
+__device__ __forceinline__ void store_pair(int64_t p, v4i t, const double (&wi)[2],
+                                           const double (&wj)[2], int32_t* __restrict__ tables,
                                            double* __restrict__ ccc) {
   if (tables) *reinterpret_cast<v4i*>(tables + 4 * p) = t;
   if (ccc) {
     double r[4];
-    pair_ccc(t, ci, cj, gamma, r);
+    pair_ccc(t, wi, wj, r);
     double2* out = reinterpret_cast<double2*>(ccc + 4 * p);
     out[0] = double2{r[0], r[1]};
     out[1] = double2{r[2], r[3]};
@@ -193,60 +219,27 @@ __device__ __forceinline__ void tri_tile(int64_t t, int64_t T, int64_t& I, int64
 
 namespace ccc {
 
-// ---------------------------------------------------------------------------
-// Tetrahedral work units for the 3-way kernels: for middle vector j, the
-// I tiles [0, ceil(j/bi)) (rows below j) times the K tiles
-// [floor((j+1)/bk), ceil(n/bk)) (columns above j).
-// ---------------------------------------------------------------------------
-// Only I tiles meeting rows [i_begin, min(j, i_end)) are kept (a staged
-// range of first indices).
-__host__ __device__ __forceinline__ int64_t units_for_j(int64_t j, int64_t n, int64_t bi,
-                                                        int64_t bk, int64_t i_begin,
-                                                        int64_t i_end) {
-  if (j < 1 || j > n - 2 || j <= i_begin) return 0;
-  const int64_t hi = j < i_end ? j : i_end;
-  if (hi <= i_begin) return 0;
-  int64_t ni = (hi + bi - 1) / bi - i_begin / bi;
-  int64_t nk = (n + bk - 1) / bk - (j + 1) / bk;
-  return ni * nk;
-}
-
-// Unit u -> (j, I tile, K tile), given offs[j] = units of all j' < j (j = 0..n).
-__device__ __forceinline__ void unit_coords(int64_t u, int64_t n, int64_t bi, int64_t bk,
-                                            int64_t i_begin, int64_t i_end,
-                                            const int64_t* __restrict__ offs, int64_t& j,
-                                            int64_t& it, int64_t& kt) {
-  int64_t lo = 0, hi = n;  // offs[lo] <= u < offs[hi]
-  while (hi - lo > 1) {
-    int64_t mid = (lo + hi) >> 1;
-    if (offs[mid] <= u) lo = mid; else hi = mid;
-  }
-  j = lo;
-  const int64_t r = u - offs[j];
-  const int64_t top = j < i_end ? j : i_end;
-  const int64_t ni = (top + bi - 1) / bi - i_begin / bi;
-  it = i_begin / bi + r % ni;
-  kt = (j + 1) / bk + r / ni;
-}
-
-}  // namespace ccc
-
-namespace ccc {
-
 void timing_begin(const char* name, hipStream_t stream);
 void timing_end(hipStream_t stream);
 
 namespace {
 
-// offs[j] = number of units of all j' < j, for j = 0..n (one workgroup).
-__global__ void unit_offsets_kernel(int64_t n, int64_t bi, int64_t bk, int64_t i_begin,
-                                    int64_t i_end, int64_t* __restrict__ offs) {
+// offs[p] = number of units of all tile pairs before p, for p = 0..pairs
+// (one workgroup; thread t walks a contiguous run of pairs).
+__global__ void unit_offsets_kernel(UnitGrid g, int64_t* __restrict__ offs) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
-  const int64_t per = (n + 1 + 1023) / 1024;
-  const int64_t lo = t * per, hi = lo + per < n + 1 ? lo + per : n + 1;
-  int64_t s = 0;
-  for (int64_t j = lo; j < hi; ++j) s += units_for_j(j, n, bi, bk, i_begin, i_end);
+  const int64_t P = grid_pairs(g);
+  const int64_t per = (P + 1023) / 1024;
+  const int64_t lo = t * per, hi = lo + per < P ? lo + per : P;
+  int64_t s = 0, it = 0, kt = 0;
+  if (lo < hi) pair_tiles(g, lo, it, kt);
+  for (int64_t p = lo; p < hi; ++p) {
+    int64_t jlo, jhi;
+    pair_j_range(g, it, kt, jlo, jhi);
+    s += jhi - jlo;
+    if (++kt == g.nt) kt = ++it;
+  }
   part[t] = s;
   __syncthreads();
   if (t == 0) {
@@ -259,30 +252,47 @@ __global__ void unit_offsets_kernel(int64_t n, int64_t bi, int64_t bk, int64_t i
   }
   __syncthreads();
   int64_t run = part[t];
-  for (int64_t j = lo; j < hi; ++j) {
-    offs[j] = run;
-    run += units_for_j(j, n, bi, bk, i_begin, i_end);
+  if (lo < hi) pair_tiles(g, lo, it, kt);
+  for (int64_t p = lo; p < hi; ++p) {
+    offs[p] = run;
+    int64_t jlo, jhi;
+    pair_j_range(g, it, kt, jlo, jhi);
+    run += jhi - jlo;
+    if (++kt == g.nt) kt = ++it;
   }
+  if (t == 1023) offs[P] = run;
 }
 
-// Launch a 3-way kernel over all its tetrahedral units (256 threads each),
-// in slices of at most 2^30 workgroups.  a.offs must hold n+1 int64.
-template <typename Kernel, typename Args>
-hipError_t launch_units(Kernel kernel, const Args& a, int64_t bi, int64_t bk, const char* name,
-                        hipStream_t stream) {
+// Units of a whole grid (host side).
+inline int64_t grid_units(const UnitGrid& g) {
   int64_t total = 0;
-  for (int64_t j = 0; j < a.n; ++j) total += units_for_j(j, a.n, bi, bk, a.i_begin, a.i_end);
+  for (int64_t it = g.it0; it < g.it1; ++it)
+    for (int64_t kt = it; kt < g.nt; ++kt) {
+      int64_t jlo, jhi;
+      pair_j_range(g, it, kt, jlo, jhi);
+      total += jhi - jlo;
+    }
+  return total;
+}
+
+// Launch a 3-way kernel over all its tetrahedral units of b x b tiles (256
+// threads each), in slices of at most 2^30 workgroups.  a.offs must hold
+// grid_pairs + 1 int64.
+template <typename Kernel, typename Args>
+hipError_t launch_units(Kernel kernel, const Args& a, int64_t b, const char* name,
+                        hipStream_t stream) {
+  const UnitGrid g = unit_grid(a.n, b, a.i_begin, a.i_end);
+  const int64_t total = grid_units(g);
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(unit_offsets_kernel, dim3(1), dim3(1024), 0, stream, a.n, bi, bk, a.i_begin,
-                     a.i_end, a.offs);
+  hipLaunchKernelGGL(unit_offsets_kernel, dim3(1), dim3(1024), 0, stream, g, a.offs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t kMaxGrid = 0x40000000;
   timing_begin(name, stream);
   for (int64_t base = 0; base < total; base += kMaxGrid) {
     int64_t cnt = total - base < kMaxGrid ? total - base : kMaxGrid;
-    hipLaunchKernelGGL(kernel, dim3((unsigned)cnt), dim3(256), 0, stream, a,
-                       (const int64_t*)a.offs, base);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)cnt), dim3(256), 0, stream, a, g,
+                       (const int64_t*)a.offs, base, cnt);
     if ((e = hipGetLastError()) != hipSuccess) break;
   }
   timing_end(stream);

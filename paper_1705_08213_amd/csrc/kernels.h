@@ -40,6 +40,95 @@ struct Pair2Args {
   Select sel;                 // threshold selection (sel.count != null) instead of dense output
 };
 
+// Row tile of the 3-way work units (both 3-way kernels use it).
+constexpr int64_t kUnitTile = 64;
+
+// Tetrahedral work units of the 3-way kernels.  Rows are cut into b-row
+// tiles; a unit is (I tile it, K tile kt, middle vector j) with it <= kt and
+// covers every triple i < j < k with i in tile it (and in the staged range
+// [i_begin, i_end)) and k in tile kt.  Units are ordered by tile pair (it
+// major, then kt) and, within a pair, by j: consecutive units share both row
+// tiles, so a run of them on one XCD reads the tiles from its L2 once.
+struct UnitGrid {
+  int64_t n, b, i_begin, i_end;
+  int64_t it0, it1;  // I tiles [it0, it1)
+  int64_t nt;        // tiles of all n rows
+};
+
+__host__ __device__ __forceinline__ UnitGrid unit_grid(int64_t n, int64_t b, int64_t i_begin,
+                                                       int64_t i_end) {
+  UnitGrid g;
+  g.n = n;
+  g.b = b;
+  g.i_begin = i_begin;
+  g.i_end = i_end;
+  g.it0 = i_begin / b;
+  g.it1 = i_end > i_begin ? (i_end + b - 1) / b : g.it0;
+  g.nt = (n + b - 1) / b;
+  return g;
+}
+
+// Number of tile pairs (it, kt), it0 <= it < it1, it <= kt < nt.
+__host__ __device__ __forceinline__ int64_t grid_pairs(const UnitGrid& g) {
+  int64_t p = 0;
+  if (g.it1 > g.it0) {
+    const int64_t rows = g.it1 - g.it0;  // sum of (nt - it) over the I tiles
+    p = rows * g.nt - (g.it1 * (g.it1 - 1) / 2 - g.it0 * (g.it0 - 1) / 2);
+  }
+  return p;
+}
+
+// First pair index of I tile it.
+__host__ __device__ __forceinline__ int64_t grid_row_start(const UnitGrid& g, int64_t it) {
+  return (it - g.it0) * g.nt - (it * (it - 1) / 2 - g.it0 * (g.it0 - 1) / 2);
+}
+
+// Middle vectors [jlo, jhi) of tile pair (it, kt): j above the first row of
+// tile it in the range, and below the last row of tile kt.
+__host__ __device__ __forceinline__ void pair_j_range(const UnitGrid& g, int64_t it, int64_t kt,
+                                                      int64_t& jlo, int64_t& jhi) {
+  jlo = (it * g.b > g.i_begin ? it * g.b : g.i_begin) + 1;
+  jhi = (kt + 1) * g.b - 1;
+  if (jhi > g.n - 1) jhi = g.n - 1;
+  if (jhi < jlo) jhi = jlo;
+}
+
+// Tile pair of pair index p.
+__host__ __device__ __forceinline__ void pair_tiles(const UnitGrid& g, int64_t p, int64_t& it,
+                                                    int64_t& kt) {
+  int64_t lo = g.it0, hi = g.it1;  // row_start(lo) <= p < row_start(hi)
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (grid_row_start(g, mid) <= p) lo = mid; else hi = mid;
+  }
+  it = lo;
+  kt = it + (p - grid_row_start(g, it));
+}
+
+// Unit u -> (j, I tile, K tile), given offs[p] = units of all pairs before p
+// (p = 0..pairs).
+__host__ __device__ __forceinline__ void unit_coords(int64_t u, const UnitGrid& g,
+                                                     const int64_t* __restrict__ offs,
+                                                     int64_t& j, int64_t& it, int64_t& kt) {
+  int64_t lo = 0, hi = grid_pairs(g);  // offs[lo] <= u < offs[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (offs[mid] <= u) lo = mid; else hi = mid;
+  }
+  pair_tiles(g, lo, it, kt);
+  int64_t jlo, jhi;
+  pair_j_range(g, it, kt, jlo, jhi);
+  j = jlo + (u - offs[lo]);
+}
+
+// Workgroup b of a grid of `count` -> unit index, so that the workgroups the
+// dispatcher sends to one of the 8 XCDs (b mod 8) take one contiguous run of
+// units, in order.
+__host__ __device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t count) {
+  const int64_t q = count >> 3, r = count & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Arguments of one 3-way tally launch over all triples i < j < k.
 struct Triple3Args {
   const uint8_t* v;
@@ -48,11 +137,15 @@ struct Triple3Args {
   double* ccc;
   const int32_t* counts;
   double gamma;
-  int64_t* offs;  // workspace: n+1 int64 (work-unit offsets per middle vector)
+  int64_t* offs;  // workspace: tile pairs + 1 int64 (work-unit offsets per tile pair)
   // triples whose first index lies in [i_begin, i_end); triple t goes to entry t - t_base
   int64_t i_begin, i_end;
   int64_t t_base;
   Select sel;
+  // Dense rho(1) Gram matrix of rows [g0, g0 + ng) (workspace), filled by the
+  // MFMA launcher; null turns the complete-data path off.
+  int32_t* gram;
+  int64_t g0, ng;
 };
 
 enum Path { kPathPopcount = 1, kPathMfma = 2 };

@@ -19,6 +19,19 @@
 // tile columns above j (tetrahedral: only i < j < k is ever stored).  A
 // workgroup is 2 x 2 waves over a (32 WI) x (32 WK) tile for one j; waves
 // whose whole tile has no valid (i, k) exit at once.
+//
+// Complete data (every row of a unit, and v_j, has all n_f fields present, as
+// the 1-way counts of the call say): with rho(0) = 2 - rho(1) on every field
+// the 8 entries follow from the single triple sum
+//   S_xyz = sum_q rho_i(1) rho_j(1) rho_k(1)
+// together with the pair sums S_xy, S_xz, S_yz (one dense rho(1) Gram matrix
+// G computed before the unit kernel), the allele counts n(1) and n_f:
+//   C(1,1,1) = S_xyz,  C(1,1,0) = 2 S_xy - S_xyz, ...,
+//   C(0,0,0) = 8 n_f - 4 (n_i + n_j + n_k) + 2 (S_xy + S_xz + S_yz) - S_xyz
+// (expand the product of (2 - x) and x factors).  One MFMA plane replaces
+// eight.  Such a unit is computed by all four waves on one 64 x 64 tile, each
+// over a quarter of the fields, and the partial sums are added through LDS.
+#include "tile2.h"
 #include "tile3.h"
 
 namespace ccc {
@@ -37,6 +50,7 @@ constexpr int WI = 2;  // 16-row blocks per wave along i
 constexpr int WK = 2;  // 16-column blocks per wave along k
 constexpr int BI = 32 * WI;
 constexpr int BK = 32 * WK;
+static_assert(BI == kUnitTile && BK == kUnitTile, "work units are kUnitTile-row tile pairs");
 
 __device__ __forceinline__ unsigned word_of(const u4& x, int s) {
   return s == 0 ? x.x : (s == 1 ? x.y : (s == 2 ? x.z : x.w));
@@ -49,20 +63,13 @@ __device__ __forceinline__ void codes4(unsigned w, unsigned (&c)[4]) {
   c[3] = (w >> 6) & kLow2;
 }
 
-__global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a,
-                                                       const int64_t* __restrict__ offs,
-                                                       int64_t unit_base) {
+// General unit, one wave: the (16 WI) x (16 WK) tile of (i, k) at rows row0..,
+// columns col0.. for middle vector j, eight MFMA planes.
+__device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, int64_t row0,
+                                             int64_t col0) {
 #pragma clang fp contract(off)
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int64_t n = a.n;
-  const int64_t u = unit_base + blockIdx.x;
-  int64_t j, it, kt;
-  unit_coords(u, n, BI, BK, a.i_begin, a.i_end, offs, j, it, kt);
-
-  const int64_t row0 = it * BI + (wave & 1) * 16 * WI;  // i range of this wave
-  const int64_t col0 = kt * BK + (wave >> 1) * 16 * WK; // k range of this wave
-  if (row0 >= j || col0 + 16 * WK - 1 <= j || col0 >= n) return;
-
   const int g = lane >> 4, rl = lane & 15;
   const uint8_t* pa[WI];
   const uint8_t* pk[WK];
@@ -153,31 +160,236 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a,
   }
 
   // Epilogue: entry 4a + 2b + c; lane holds rows 4g + e of column rl.
-  double wj[2];
-  vector_factors(a.counts, j, a.gamma, wj);
+  double wj[2], wk[WK][2];
+  triple_factors(a, j, wj);
+#pragma unroll
+  for (int c = 0; c < WK; ++c) triple_factors(a, col0 + 16 * c + rl, wk[c]);
 #pragma unroll
   for (int m = 0; m < WI; ++m)
 #pragma unroll
-    for (int c = 0; c < WK; ++c) {
-      const int64_t k = col0 + 16 * c + rl;
-      const bool kvalid = k > j && k < n;
-      double wk[2];
-      vector_factors(a.counts, kvalid ? k : j, a.gamma, wk);
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = row0 + 16 * m + 4 * g + e;
+      double wi[2];
+      triple_factors(a, i, wi);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t i = row0 + 16 * m + 4 * g + e;
+      for (int c = 0; c < WK; ++c) {
+        const int64_t k = col0 + 16 * c + rl;
         int t[8];
 #pragma unroll
         for (int x = 0; x < 8; ++x) t[x] = acc[m][c][x][e];
-        emit_triple(a, kvalid && i < j, i, j, k, t, wj, wk);
+        emit_triple(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c]);
       }
     }
+}
+
+// Complete-data unit (see the notes at the top): all four waves build the
+// same 64 x 64 tile of S_xyz over a quarter of the 256-field super-steps
+// each, the partial sums meet in LDS, and wave w finishes rows 16w..16w+15.
+__device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, int64_t i0,
+                                              int64_t k0, v4i (*part)[16][64]) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, rl = lane & 15;
+  const int64_t n = a.n;
+  const uint8_t* pa[4];
+  const uint8_t* pk[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    int64_t rr = i0 + 16 * m + rl;
+    pa[m] = a.v + (rr < n ? rr : n - 1) * a.ld + 16 * g;
+    rr = k0 + 16 * m + rl;
+    pk[m] = a.v + (rr < n ? rr : n - 1) * a.ld + 16 * g;
+  }
+  const uint8_t* pj = a.v + j * a.ld + 16 * g;
+
+  v4i acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[m][c] = v4i{0, 0, 0, 0};
+
+  const int64_t steps = (a.n_f + 255) / 256;
+  const int64_t s_end = steps * (wave + 1) / 4;
+  for (int64_t st = steps * wave / 4; st < s_end; ++st) {
+    const int64_t kb = st * 64;
+    const bool full = (kb + 64) * 4 <= a.n_f;
+    u4 xa[4], xk[4], xj;
+    if (full) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        xa[m] = *reinterpret_cast<const u4*>(pa[m] + kb);
+        xk[m] = *reinterpret_cast<const u4*>(pk[m] + kb);
+      }
+      xj = *reinterpret_cast<const u4*>(pj + kb);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        xa[m] = load_fields64(pa[m] - 16 * g, kb + 16 * g, a.n_f);
+        xk[m] = load_fields64(pk[m] - 16 * g, kb + 16 * g, a.n_f);
+      }
+      xj = load_fields64(pj - 16 * g, kb + 16 * g, a.n_f);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      unsigned cj[4], sel1[4];
+      codes4(word_of(xj, s), cj);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) sel1[t] = __builtin_amdgcn_perm(0u, kSelJ1, cj[t]);
+      v4i A1[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) A1[m] = tile2::unpack16_rho1(word_of(xa[m], s));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        unsigned ck[4];
+        codes4(word_of(xk[c], s), ck);
+        v4i M;  // rho_j(1) rho_k(1)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          M[t] = (int)__builtin_amdgcn_perm(kRho1Twice, kRho1Table, ck[t] | sel1[t]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          acc[m][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[m], M, acc[m][c], 0, 0, 0);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) part[wave][4 * m + c][lane] = acc[m][c];
+  __syncthreads();
+
+  // Rows i0 + 16 wave + 4g + e, columns k0 + 16c + rl.
+  const v4i* cnt = reinterpret_cast<const v4i*>(a.counts);
+  const int64_t ng = a.ng, g0 = a.g0;
+  const unsigned S8 = 8u * (unsigned)a.n_f, Y = (unsigned)cnt[j].y;
+  const int32_t* grow_j = a.gram + (j - g0) * ng;
+  double wj[2], wk[4][2];
+  triple_factors(a, j, wj);
+  v4i xyz[4];
+  unsigned Z[4], YZ[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    xyz[c] = part[0][4 * wave + c][lane] + part[1][4 * wave + c][lane] +
+             part[2][4 * wave + c][lane] + part[3][4 * wave + c][lane];
+    const int64_t k = k0 + 16 * c + rl;
+    const int64_t kk = k > j && k < n ? k : j;  // a valid row for invalid lanes
+    triple_factors(a, kk, wk[c]);
+    Z[c] = (unsigned)cnt[kk].y;
+    YZ[c] = (unsigned)grow_j[kk - g0];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = i0 + 16 * wave + 4 * g + e;
+    const int64_t ii = i < j ? i : j;  // a valid row for invalid lanes
+    double wi[2];
+    triple_factors(a, ii, wi);
+    const unsigned X = (unsigned)cnt[ii].y;
+    const int32_t* grow_i = a.gram + (ii - g0) * ng;
+    const unsigned XY = (unsigned)grow_i[j - g0];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t k = k0 + 16 * c + rl;
+      const bool valid = k > j && k < n && i < j;
+      const int64_t kk = k > j && k < n ? k : j;
+      const unsigned XZ = (unsigned)grow_i[kk - g0];
+      const unsigned XYZ = (unsigned)xyz[c][e];
+      int t[8];
+      t[7] = (int)XYZ;
+      t[6] = (int)(2u * XY - XYZ);
+      t[5] = (int)(2u * XZ - XYZ);
+      t[3] = (int)(2u * YZ[c] - XYZ);
+      t[4] = (int)(4u * X - 2u * XY - 2u * XZ + XYZ);
+      t[2] = (int)(4u * Y - 2u * XY - 2u * YZ[c] + XYZ);
+      t[1] = (int)(4u * Z[c] - 2u * XZ - 2u * YZ[c] + XYZ);
+      t[0] = (int)(S8 - 4u * (X + Y + Z[c]) + 2u * (XY + XZ + YZ[c]) - XYZ);
+      emit_triple(a, valid, i, j, k, t, wi, wj, wk[c]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid ug,
+                                                       const int64_t* __restrict__ offs,
+                                                       int64_t unit_base, int64_t count) {
+  __shared__ v4i part[4][16][64];
+  const int wave = threadIdx.x >> 6;
+  const int64_t n = a.n;
+  const int64_t u = unit_base + xcd_unit(blockIdx.x, count);
+  int64_t j, it, kt;
+  unit_coords(u, ug, offs, j, it, kt);
+
+  // Complete-data vote over the unit's 64 i rows, 64 k rows and v_j
+  // (workgroup-uniform; rows past n repeat row n-1).
+  if (a.gram && a.n_f > 0) {
+    const int t = threadIdx.x;
+    int64_t r = t < 64 ? it * BI + t : (t < 128 ? kt * BK + (t - 64) : j);
+    r = r < n ? r : n - 1;
+    const bool ok = reinterpret_cast<const v4i*>(a.counts)[r].z == a.n_f;
+    if (__syncthreads_and(ok ? 1 : 0)) {
+      complete_unit(a, j, it * BI, kt * BK, part);
+      return;
+    }
+  }
+
+  const int64_t row0 = it * BI + (wave & 1) * 16 * WI;  // i range of this wave
+  const int64_t col0 = kt * BK + (wave >> 1) * 16 * WK; // k range of this wave
+  if (row0 >= j || col0 + 16 * WK - 1 <= j || col0 >= n) return;
+  general_wave(a, j, row0, col0);
+}
+
+// G[r][c] = sum_q rho_{g0+r,q}(1) rho_{g0+c,q}(1) for r, c < ng: the pair
+// sums of the complete-data formula.  Waves of 64 x 32 entries, workgroups
+// of 128 x 64.
+__global__ __launch_bounds__(256, 2) void gram1_kernel(const uint8_t* __restrict__ v, int64_t ld,
+                                                       int64_t g0, int64_t ng, int64_t n_f,
+                                                       int32_t* __restrict__ gram) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, rl = lane & 15;
+  const int64_t row0 = (int64_t)blockIdx.y * 128 + (wave & 1) * 64;
+  const int64_t col0 = (int64_t)blockIdx.x * 64 + (wave >> 1) * 32;
+  if (row0 >= ng || col0 >= ng) return;
+  const uint8_t* pa[4];
+  const uint8_t* pb[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    int64_t r = row0 + 16 * m + rl;
+    pa[m] = v + (g0 + (r < ng ? r : ng - 1)) * ld + 16 * g;
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    int64_t r = col0 + 16 * c + rl;
+    pb[c] = v + (g0 + (r < ng ? r : ng - 1)) * ld + 16 * g;
+  }
+  v4i acc[4][2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[m][c] = v4i{0, 0, 0, 0};
+  tile2::wave_loop<4, 2>(pa, pb, g, n_f, [&](const u4 (&ca)[4], const u4 (&cb)[2]) {
+    tile2::mma_superstep_rho1<4, 2>(ca, cb, acc);
+  });
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = row0 + 16 * m + 4 * g + e, col = col0 + 16 * c + rl;
+        if (r < ng && col < ng) gram[r * ng + col] = acc[m][c][e];
+      }
 }
 
 }  // namespace
 
 hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream) {
-  return launch_units(mfma3_kernel, a, BI, BK, "mfma3", stream);
+  if (a.gram && a.ng > 0) {
+    const dim3 grid((unsigned)((a.ng + 63) / 64), (unsigned)((a.ng + 127) / 128));
+    hipLaunchKernelGGL(gram1_kernel, grid, dim3(256), 0, stream, a.v, a.ld, a.g0, a.ng, a.n_f,
+                       a.gram);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_units(mfma3_kernel, a, BI, "mfma3", stream);
 }
 
 }  // namespace ccc

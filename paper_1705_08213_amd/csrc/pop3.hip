@@ -18,6 +18,7 @@ namespace ccc {
 namespace {
 
 constexpr int kTile = 64;
+static_assert(kTile == kUnitTile, "work units are kUnitTile-row tile pairs");
 constexpr int kStageWords = 8;
 
 __device__ __forceinline__ void make_planes(unsigned w0, unsigned w1, unsigned& p, unsigned& o,
@@ -29,8 +30,9 @@ __device__ __forceinline__ void make_planes(unsigned w0, unsigned w1, unsigned& 
   p = ~(b1 & ~b0);
 }
 
-__global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t* __restrict__ offs,
-                                                   int64_t unit_base) {
+__global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, UnitGrid ug,
+                                                   const int64_t* __restrict__ offs,
+                                                   int64_t unit_base, int64_t count) {
 #pragma clang fp contract(off)
   __shared__ unsigned sP[2][kStageWords][kTile], sO[2][kStageWords][kTile],
       sH[2][kStageWords][kTile];
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
 
   const int64_t n = a.n;
   int64_t j, it, kt;
-  unit_coords(unit_base + blockIdx.x, n, kTile, kTile, a.i_begin, a.i_end, offs, j, it, kt);
+  unit_coords(unit_base + xcd_unit(blockIdx.x, count), ug, offs, j, it, kt);
   const int64_t I0 = it * kTile, K0 = kt * kTile;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
 
@@ -119,14 +121,16 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
     }
   }
 
-  double wj[2];
-  vector_factors(a.counts, j, a.gamma, wj);
+  double wj[2], wi[4][2];
+  triple_factors(a, j, wj);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) triple_factors(a, I0 + ty + 16 * r, wi[r]);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int64_t k = K0 + tx + 16 * c;
     const bool kvalid = k > j && k < n;
     double wk[2];
-    vector_factors(a.counts, kvalid ? k : j, a.gamma, wk);
+    triple_factors(a, k, wk);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t i = I0 + ty + 16 * r;
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
             }
         tab[e] = (int)s;
       }
-      emit_triple(a, kvalid && i < j, i, j, k, tab, wj, wk);
+      emit_triple(a, kvalid && i < j, i, j, k, tab, wi[r], wj, wk);
     }
   }
 }
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256) void pop3_kernel(Triple3Args a, const int64_t*
 }  // namespace
 
 hipError_t launch_pop3(const Triple3Args& a, hipStream_t stream) {
-  return launch_units(pop3_kernel, a, kTile, kTile, "pop3", stream);
+  return launch_units(pop3_kernel, a, kTile, "pop3", stream);
 }
 
 }  // namespace ccc

@@ -9,14 +9,15 @@
 namespace ccc {
 namespace tile2 {
 
-// Output of one pair (i, j) with table t (Eqs. (2)-(3)).  Dense mode stores
-// the table and/or CCC at entry p(i,j) - p_base (adding the old table first
-// when accumulating); selection mode keeps the pair only if one of its CCC
-// values reaches the threshold.  In selection mode every lane of the wave
-// must call it (the slot is taken with one atomic per wave); `valid` says
-// whether this lane holds a pair to emit.
+// Output of one pair (i, j) with table t (Eqs. (2)-(3)) and the factors wi,
+// wj of its two vectors (read on valid lanes only).  Dense mode stores the
+// table and/or CCC at entry p(i,j) - p_base (adding the old table first when
+// accumulating); selection mode keeps the pair only if one of its CCC values
+// reaches the threshold.  In selection mode every lane of the wave must call
+// it (the slot is taken with one atomic per wave); `valid` says whether this
+// lane holds a pair to emit.
 __device__ __forceinline__ void emit_pair(const Pair2Args& a, bool valid, int64_t i, int64_t j,
-                                          v4i t) {
+                                          v4i t, const double (&wi)[2], const double (&wj)[2]) {
   valid = valid && i >= a.row_begin && i < a.row_end;
   if (a.sel.count) {
     double r[4] = {0.0, 0.0, 0.0, 0.0};
@@ -24,8 +25,7 @@ __device__ __forceinline__ void emit_pair(const Pair2Args& a, bool valid, int64_
     int64_t p = 0;
     if (valid) {
       p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
-      pair_ccc(t, reinterpret_cast<const v4i*>(a.counts_a)[i],
-               reinterpret_cast<const v4i*>(a.counts_b)[j], a.gamma, r);
+      pair_ccc(t, wi, wj, r);
       keep = r[0] >= a.sel.threshold || r[1] >= a.sel.threshold ||
              r[2] >= a.sel.threshold || r[3] >= a.sel.threshold;
     }
@@ -42,8 +42,19 @@ __device__ __forceinline__ void emit_pair(const Pair2Args& a, bool valid, int64_
   if (!valid) return;
   const int64_t p = a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j;
   if (a.accumulate) t = t + *reinterpret_cast<const v4i*>(a.tables + 4 * p);
-  store_pair(p - a.p_base, t, reinterpret_cast<const v4i*>(a.counts_a)[i],
-             reinterpret_cast<const v4i*>(a.counts_b)[j], a.gamma, a.tables, a.ccc);
+  store_pair(p - a.p_base, t, wi, wj, a.tables, a.ccc);
+}
+
+// Factors of row x of A (side 0) or B (side 1), clamped into range; only
+// computed when some CCC value is produced.
+__device__ __forceinline__ void side_factors(const Pair2Args& a, int side, int64_t x,
+                                             double (&w)[2]) {
+  if (a.ccc || a.sel.count) {
+    const int64_t n = side ? a.n_b : a.n_a;
+    vector_factors(side ? a.counts_b : a.counts_a, x < n ? x : n - 1, a.gamma, w);
+  } else {
+    w[0] = w[1] = 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -239,20 +250,30 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
       mma_superstep_rho1<WM, WN>(ca, cb, acc1);
     });
     const int nf4 = (int)(4 * a.n_f);
+    double wj[WN][2];
+    int n1j[WN];
+#pragma unroll
+    for (int n = 0; n < WN; ++n) {
+      const int64_t j = col0 + 16 * n + rl;
+      side_factors(a, 1, j, wj[n]);
+      n1j[n] = reinterpret_cast<const v4i*>(a.counts_b)[j < a.n_b ? j : a.n_b - 1].y;
+    }
 #pragma unroll
     for (int m = 0; m < WM; ++m)
 #pragma unroll
-      for (int n = 0; n < WN; ++n) {
-        const int64_t j = col0 + 16 * n + rl;
-        const int n1j = reinterpret_cast<const v4i*>(a.counts_b)[j < a.n_b ? j : a.n_b - 1].y;
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = row0 + 16 * m + 4 * g + e;
+        const int n1i = reinterpret_cast<const v4i*>(a.counts_a)[i < a.n_a ? i : a.n_a - 1].y;
+        double wi[2];
+        side_factors(a, 0, i, wi);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t i = row0 + 16 * m + 4 * g + e;
-          const int n1i = reinterpret_cast<const v4i*>(a.counts_a)[i < a.n_a ? i : a.n_a - 1].y;
+        for (int n = 0; n < WN; ++n) {
+          const int64_t j = col0 + 16 * n + rl;
           const int c11 = acc1[m][n][e];
           const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
           emit_pair(a, valid, i, j,
-                    v4i{nf4 - 2 * n1i - 2 * n1j + c11, 2 * n1j - c11, 2 * n1i - c11, c11});
+                    v4i{nf4 - 2 * n1i - 2 * n1j[n] + c11, 2 * n1j[n] - c11, 2 * n1i - c11, c11},
+                    wi, wj[n]);
         }
       }
     return;
@@ -271,17 +292,25 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
 
   // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
 #pragma unroll
-  for (int m = 0; m < WM; ++m)
+  for (int m = 0; m < WM; ++m) {
+    double wi[4][2];
 #pragma unroll
-    for (int n = 0; n < WN; ++n)
+    for (int e = 0; e < 4; ++e) side_factors(a, 0, row0 + 16 * m + 4 * g + e, wi[e]);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) {
+      const int64_t j = col0 + 16 * n + rl;
+      double wj[2];
+      side_factors(a, 1, j, wj);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i = row0 + 16 * m + 4 * g + e;
-        const int64_t j = col0 + 16 * n + rl;
         const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
         emit_pair(a, valid, i, j,
-                  v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]});
+                  v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]},
+                  wi[e], wj);
       }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -404,9 +433,14 @@ __device__ __forceinline__ void pop2_tile_body(const Pair2Args& a, int64_t I, in
     }
   }
 
+  double wj[4][2];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) side_factors(a, 1, J0 + tx + 16 * c, wj[c]);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t i = I0 + ty + 16 * r;
+    double wi[2];
+    side_factors(a, 0, i, wi);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t j = J0 + tx + 16 * c;
@@ -419,7 +453,8 @@ __device__ __forceinline__ void pop2_tile_body(const Pair2Args& a, int64_t I, in
         xpp = (int)a.n_f;
       }
       emit_pair(a, valid, i, j,
-                v4i{4 * xpp - 2 * xp1 - 2 * x1p + x11, 2 * xp1 - x11, 2 * x1p - x11, x11});
+                v4i{4 * xpp - 2 * xp1 - 2 * x1p + x11, 2 * xp1 - x11, 2 * x1p - x11, x11}, wi,
+                wj[c]);
     }
   }
 }

@@ -18,30 +18,35 @@ __device__ __forceinline__ void triple_ccc(const int (&t)[8], const double (&wi)
   for (int x = 0; x < 8; ++x) sum += t[x];
   const int m_ijk = sum >> 3;  // fields where all three are present
   if (m_ijk > 0) {
-    const double den = 8.0 * (double)m_ijk;
+    const double den = 8.0 * (double)m_ijk, y = 1.0 / den;
 #pragma unroll
     for (int x = 0; x < 8; ++x)
-      r[x] = ((double)t[x] / den) * wi[x >> 2] * wj[(x >> 1) & 1] * wk[x & 1];
+      r[x] = quot_rn((double)t[x], den, y) * wi[x >> 2] * wj[(x >> 1) & 1] * wk[x & 1];
   } else {
 #pragma unroll
     for (int x = 0; x < 8; ++x) r[x] = 0.0;
   }
 }
 
-__device__ __forceinline__ void vector_factors(const int32_t* __restrict__ counts, int64_t x,
-                                               double gamma, double (&w)[2]) {
-  const v4i c = reinterpret_cast<const v4i*>(counts)[x];
-  w[0] = one_minus_gf(c.x, c.z, gamma);
-  w[1] = one_minus_gf(c.y, c.z, gamma);
+// Factors of vector x (clamped into range); only computed when some CCC value
+// is produced.
+__device__ __forceinline__ void triple_factors(const Triple3Args& a, int64_t x, double (&w)[2]) {
+  if (a.ccc || a.sel.count) {
+    vector_factors(a.counts, x < a.n ? x : a.n - 1, a.gamma, w);
+  } else {
+    w[0] = w[1] = 0.0;
+  }
 }
 
 // Dense mode: table and/or CCC at entry T(i,j,k) - t_base.  Selection mode:
 // keep the triple if one of its CCC values reaches the threshold; then every
 // lane of the wave must call (one atomic per wave) and `valid` marks lanes
-// that hold a triple.  wj / wk are the factors of j and k (valid lanes only).
+// that hold a triple.  wi / wj / wk are the factors of i, j and k (read on
+// valid lanes only).
 __device__ __forceinline__ void emit_triple(const Triple3Args& a, bool valid, int64_t i,
                                             int64_t j, int64_t k, const int (&t)[8],
-                                            const double (&wj)[2], const double (&wk)[2]) {
+                                            const double (&wi)[2], const double (&wj)[2],
+                                            const double (&wk)[2]) {
   valid = valid && i >= a.i_begin && i < a.i_end;
   if (a.sel.count) {
     double r[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -49,8 +54,6 @@ __device__ __forceinline__ void emit_triple(const Triple3Args& a, bool valid, in
     int64_t p = 0;
     if (valid) {
       p = triple_index(a.n, i, j, k);
-      double wi[2];
-      vector_factors(a.counts, i, a.gamma, wi);
       triple_ccc(t, wi, wj, wk, r);
 #pragma unroll
       for (int x = 0; x < 8; ++x) keep = keep || r[x] >= a.sel.threshold;
@@ -77,8 +80,7 @@ __device__ __forceinline__ void emit_triple(const Triple3Args& a, bool valid, in
     o[1] = v4i{t[4], t[5], t[6], t[7]};
   }
   if (a.ccc) {
-    double wi[2], r[8];
-    vector_factors(a.counts, i, a.gamma, wi);
+    double r[8];
     triple_ccc(t, wi, wj, wk, r);
     double2* c = reinterpret_cast<double2*>(a.ccc + 8 * p);
 #pragma unroll

@@ -34,6 +34,19 @@ def assert_ccc_close(got: np.ndarray, want: np.ndarray, rtol=1e-12):
                              f"got {got[bad][:5]} want {want[bad][:5]}")
 
 
+def assert_ccc_identical(got: np.ndarray, want: np.ndarray):
+    """The same doubles bit for bit (the epilogue rounds every quotient and
+    product as the oracle's plain formula does)."""
+    got = np.ascontiguousarray(got, dtype=np.float64)
+    want = np.ascontiguousarray(want, dtype=np.float64)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    diff = got.view(np.uint64) != want.view(np.uint64)
+    if diff.any():
+        idx = np.argwhere(diff)[:5]
+        raise AssertionError(f"{int(diff.sum())} CCC values not bit-identical, first at "
+                             f"{idx.tolist()}: got {got[diff][:5]!r} want {want[diff][:5]!r}")
+
+
 def assert_tables_equal(got: np.ndarray, want: np.ndarray):
     got = np.asarray(got).astype(np.int64)
     want = np.asarray(want).astype(np.int64)

@@ -1,0 +1,81 @@
+// Host-side check of the 3-way work-unit enumeration (UnitGrid helpers of
+// the library's kernels.h, compiled for the host): for each case, the units
+// cover every triple i < j < k with i in [i_begin, min(i_end, n-2)) exactly
+// once, every unit lies inside its tile pair, and the XCD remap of a grid is
+// a permutation.  Prints "ok <cases>" and exits 0, or names the first failure.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <vector>
+
+#include "../../paper_1705_08213_amd/csrc/kernels.h"
+
+using namespace ccc;
+
+static int fail(const char* what, long n, long ib, long ie) {
+  printf("FAIL %s n=%ld i_begin=%ld i_end=%ld\n", what, n, ib, ie);
+  return 1;
+}
+
+static int check(int64_t n, int64_t ib, int64_t ie, int64_t b) {
+  const int64_t row_end = ie < n - 2 ? ie : n - 2;
+  if (row_end <= ib) return 0;
+  const UnitGrid g = unit_grid(n, b, ib, row_end);
+  const int64_t P = grid_pairs(g);
+  std::vector<int64_t> offs(P + 1, 0);
+  for (int64_t p = 0; p < P; ++p) {
+    int64_t it, kt, jlo, jhi;
+    pair_tiles(g, p, it, kt);
+    if (it < g.it0 || it >= g.it1 || kt < it || kt >= g.nt) return fail("pair_tiles", n, ib, ie);
+    pair_j_range(g, it, kt, jlo, jhi);
+    offs[p + 1] = offs[p] + (jhi - jlo);
+  }
+  const int64_t U = offs[P];
+  std::vector<unsigned char> seen(U, 0);
+  for (int64_t w = 0; w < U; ++w) {
+    const int64_t u = xcd_unit(w, U);
+    if (u < 0 || u >= U || seen[u]) return fail("xcd_unit", n, ib, ie);
+    seen[u] = 1;
+  }
+  // cover[i][j][k] as a flat count over the staged triples
+  std::vector<unsigned char> cover((size_t)n * n * n, 0);
+  for (int64_t u = 0; u < U; ++u) {
+    int64_t j, it, kt, jlo, jhi;
+    unit_coords(u, g, offs.data(), j, it, kt);
+    pair_j_range(g, it, kt, jlo, jhi);
+    if (j < jlo || j >= jhi || j < 1 || j > n - 2) return fail("unit_coords", n, ib, ie);
+    for (int64_t i = it * b; i < (it + 1) * b && i < j; ++i) {
+      if (i < ib || i >= row_end) continue;
+      for (int64_t k = kt * b; k < (kt + 1) * b && k < n; ++k)
+        if (k > j) ++cover[((size_t)i * n + j) * n + k];
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i + 1; j < n; ++j)
+      for (int64_t k = j + 1; k < n; ++k) {
+        const int want = (i >= ib && i < row_end) ? 1 : 0;
+        if (cover[((size_t)i * n + j) * n + k] != want) return fail("coverage", n, ib, ie);
+      }
+  return 0;
+}
+
+int main() {
+  const long cases[][3] = {{3, 0, 3},      {4, 0, 4},      {5, 0, 5},     {64, 0, 64},
+                           {65, 0, 65},    {66, 0, 66},    {130, 0, 130}, {150, 5, 64},
+                           {150, 64, 70},  {150, 70, 129}, {150, 129, 150}, {90, 0, 5},
+                           {90, 88, 90},   {200, 63, 65},  {200, 127, 128}, {197, 0, 197}};
+  int count = 0;
+  for (const auto& c : cases) {
+    if (check(c[0], c[1], c[2], 64)) return 1;
+    ++count;
+  }
+  srand(7);
+  for (int r = 0; r < 30; ++r) {
+    const long n = 3 + rand() % 180, ib = rand() % (n + 1), ie = ib + rand() % (n + 1 - ib);
+    const long b = (r & 1) ? 64 : 16;
+    if (check(n, ib, ie, b)) return 1;
+    ++count;
+  }
+  printf("ok %d\n", count);
+  return 0;
+}

@@ -7,7 +7,8 @@ import oracle
 import oracle.brute
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import assert_ccc_close, assert_tables_equal, dev, host, say
+from gpu_util import (assert_ccc_close, assert_ccc_identical, assert_tables_equal, dev, host,
+                      say)
 
 pytestmark = pytest.mark.gpu
 
@@ -130,3 +131,15 @@ def test_2way_complete_data_and_single_missing_entry(path, n_v, n_f):
     ot2, oc2 = oracle.two_way(v2, n_f)
     assert_tables_equal(t2, ot2)
     assert_ccc_close(c2, oc2)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("missing", [0.0, 0.01, 0.3])
+def test_2way_ccc_bit_identical_to_oracle(path, missing):
+    """Beyond the 1e-12 contract: the shared-reciprocal quotient is the
+    correctly rounded t/den, so every CCC double equals the oracle's."""
+    say("2way bit-identical", path, missing)
+    v = synth.beta_hw(300, 2500, seed=41, missing=missing)
+    _, c, _ = run2(v, 2500, path)
+    _, oc = oracle.two_way(v, 2500)
+    assert_ccc_identical(c, oc)

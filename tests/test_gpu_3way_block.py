@@ -3,9 +3,11 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.brute
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import assert_ccc_close, assert_tables_equal, dev, host, say
+from gpu_util import (assert_ccc_close, assert_ccc_identical, assert_tables_equal, dev, host,
+                      say)
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +49,76 @@ def test_3way_closed_form_and_zero_fields(path):
     t0, c0, _ = ccc.ccc_3way(dev(v0), 0, path=path)
     sync()
     assert np.all(host(t0) == 0) and np.all(host(c0) == 0.0)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n_v,n_f", [(70, 1000), (130, 3001), (66, 100), (140, 257), (5, 9)])
+def test_3way_complete_data_and_single_missing_entry(path, n_v, n_f):
+    """Complete inputs take the one-plane MFMA form in every 64 x 64 unit
+    (four waves over quarters of the fields, tail included); one missing entry
+    sends only the units that hold its row (as i, j or k) to the general form."""
+    say("3way complete", path, n_v, n_f)
+    v = synth.beta_hw(n_v, n_f, seed=300 + n_v, missing=0.0)
+    t, c, _ = ccc.ccc_3way(dev(v), n_f, path=path)
+    sync()
+    ot, oc = oracle.three_way(v, n_f)
+    assert_tables_equal(host(t), ot)
+    assert_ccc_close(host(c), oc)
+    codes = oracle.brute.unpack_codes(v, n_f)
+    codes[n_v // 2, n_f // 3] = 2  # one missing entry
+    v2 = synth.pack_codes(codes, pad_value=-1)
+    t2, c2, _ = ccc.ccc_3way(dev(v2), n_f, path=path)
+    sync()
+    ot2, oc2 = oracle.three_way(v2, n_f)
+    assert_tables_equal(host(t2), ot2)
+    assert_ccc_close(host(c2), oc2)
+
+
+def test_3way_complete_data_rows_and_select():
+    """Row ranges whose first row is not on a 64-row unit boundary (the pair
+    sums then start at the unit boundary below it) and threshold selection,
+    on complete data."""
+    import torch
+    n, n_f = 150, 777
+    say("3way complete rows/select")
+    v = synth.beta_hw(n, n_f, seed=905, missing=0.0)
+    dv = dev(v)
+    t_full, c_full, _ = ccc.ccc_3way(dv, n_f, path="mfma")
+    parts = []
+    for i0, i1 in [(0, 5), (5, 64), (64, 70), (70, 129), (129, 150)]:
+        t, c, _ = ccc.ccc_3way_rows(dv, n_f, i0, i1, path="mfma")
+        sync()
+        ot, oc = oracle.three_way(v, n_f, i0, i1)
+        assert_tables_equal(host(t), ot)
+        assert_ccc_close(host(c), oc)
+        if len(ot):
+            parts.append((t, c))
+    assert torch.equal(torch.cat([p[0] for p in parts]), t_full)
+    assert torch.equal(torch.cat([p[1] for p in parts]), c_full)
+    ot, oc = oracle.three_way(v, n_f)
+    mx = oc.max(axis=1)
+    u = np.unique(mx)
+    thr = 0.5 * (u[-51] + u[-50])
+    want = np.flatnonzero(mx >= thr)
+    found, idx, cc, tt = ccc.ccc_3way_select(dv, n_f, thr, cap=len(want), path="mfma")
+    assert found == len(want)
+    idx, cc, tt = host(idx), host(cc), host(tt)
+    order = np.argsort(idx)
+    assert np.array_equal(idx[order], want)
+    assert_tables_equal(tt[order], ot[want])
+    assert_ccc_close(cc[order], oc[want])
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("missing", [0.0, 0.01, 0.3])
+def test_3way_ccc_bit_identical_to_oracle(path, missing):
+    """Beyond the 1e-12 contract: every CCC double equals the oracle's."""
+    say("3way bit-identical", path, missing)
+    v = synth.beta_hw(100, 1500, seed=42, missing=missing)
+    _, c, _ = ccc.ccc_3way(dev(v), 1500, path=path)
+    sync()
+    _, oc = oracle.three_way(v, 1500)
+    assert_ccc_identical(host(c), oc)
 
 
 def test_3way_paths_agree():

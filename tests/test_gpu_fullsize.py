@@ -121,6 +121,45 @@ def test_c3_3way_full_size():
     assert np.array_equal(total, oracle.fp3_from_input(v, n_f, w, u, z))
 
 
+def test_c3_shape_complete_data_full_size():
+    """The 3-way shape with no missing entries: every unit takes the one-plane
+    complete-data form.  Sampled triples against the oracle one by one, every
+    table through the whole-output checksum."""
+    n_v, n_f = 2048, 16384
+    say("c3 complete: generate")
+    v = synth.beta_hw(n_v, n_f, seed=0, missing=0.0)
+    dv = dev(v)
+    say("c3 complete: mfma ccc_3way")
+    t, c, cnt = ccc.ccc_3way(dv, n_f, path="mfma")
+    sync()
+    assert int(cnt[:, 2].min()) == n_f
+    rng = np.random.default_rng(13)
+    tri = set()
+    for _ in range(1500):
+        x = np.sort(rng.choice(n_v, 3, replace=False))
+        tri.add(tuple(int(y) for y in x))
+    for j in (1, 63, 64, 65, 127, 128, 1000, 2046):
+        tri.add((j - 1, j, j + 1))
+        tri.add((0, j, n_v - 1))
+    ii, jj, kk = (np.array(z, dtype=np.int64) for z in zip(*sorted(tri)))
+    say("c3 complete: sampled triples", len(ii))
+    ot, oc = oracle.triples_list(v, n_f, ii, jj, kk)
+    p = [oracle.triple_index(n_v, int(a), int(b), int(d)) for a, b, d in zip(ii, jj, kk)]
+    assert_tables_equal(gather_rows(t, p), ot)
+    assert_ccc_close(gather_rows(c, p), oc)
+    del c
+    say("c3 complete: checksum over slices")
+    w, u, z = (synth.weights(n_v, seed=14, tag=k) for k in range(3))
+    total = np.zeros(8, dtype=np.uint64)
+    T = t.shape[0]
+    step = 1 << 27
+    for s in range(0, T, step):
+        e = min(T, s + step)
+        total = oracle.fp_add(total, oracle.fp3_from_tables(t[s:e].cpu().numpy(), n_v, w, u, z,
+                                                            t_begin=s))
+    assert np.array_equal(total, oracle.fp3_from_input(v, n_f, w, u, z))
+
+
 def test_c5_block_full_size_chunked():
     import torch
     n, n_f, chunk = 16384, 131072, 16384
