@@ -61,6 +61,15 @@ def _lib():
         lib.oracle_pair_index.restype = i64
         lib.oracle_triple_index.argtypes = [i64, i64, i64, i64]
         lib.oracle_triple_index.restype = i64
+        lib.oracle_multi_invalid.argtypes = [ptr, i64, i64, i64, cint]
+        lib.oracle_multi_invalid.restype = i64
+        lib.oracle_multi_counts1.argtypes = [ptr, i64, i64, i64, cint, ptr]
+        lib.oracle_multi_2way_rows.argtypes = [ptr, i64, i64, i64, cint, i64, i64, ptr, dbl, ptr,
+                                               ptr]
+        lib.oracle_multi_2way_list.argtypes = [ptr, i64, i64, cint, ptr, ptr, i64, ptr, dbl, ptr,
+                                               ptr]
+        lib.oracle_multi_fp2_from_input.argtypes = [ptr, i64, i64, i64, cint, ptr, ptr, ptr]
+        lib.oracle_multi_fp2_from_tables.argtypes = [ptr, i64, cint, ptr, ptr, ptr]
         lib.oracle_num_threads.restype = cint
         lib.oracle_set_num_threads.argtypes = [cint]
         _lib_handle = lib
@@ -259,3 +268,77 @@ P61 = (1 << 61) - 1
 def fp_add(a, b) -> np.ndarray:
     """Element-wise (a + b) mod 2^61-1 for checksum vectors."""
     return np.array([(int(x) + int(y)) % P61 for x, y in zip(a, b)], dtype=np.uint64)
+
+
+# ---------------------------------------------------------------------------
+# Multi-allelic 2-way CCC (s states per marker, one byte per field; see the
+# multi-allelic section of ccc_oracle.c).
+# ---------------------------------------------------------------------------
+
+def multi_invalid(v, n_f, s) -> int:
+    """Number of entries that are neither a genotype over the first s states
+    nor the missing byte 0."""
+    v = _c(v, np.uint8)
+    return int(_lib().oracle_multi_invalid(v.ctypes.data, v.shape[0], n_f, v.shape[1], s))
+
+
+def multi_counts1(v, n_f, s) -> np.ndarray:
+    """int64 [n_v, 5]: n_i(0..3) (0 for states >= s) and m_i."""
+    v = _c(v, np.uint8)
+    out = np.zeros((v.shape[0], 5), dtype=np.int64)
+    if v.shape[0]:
+        _lib().oracle_multi_counts1(v.ctypes.data, v.shape[0], n_f, v.shape[1], s,
+                                    out.ctypes.data)
+    return out
+
+
+def multi_two_way(v, n_f, s, i0=0, i1=None, gamma=GAMMA, with_ccc=True):
+    """Tables int64 [P, s*s] and CCC double [P, s*s] (entry a*s + b) for the
+    pairs whose first index lies in [i0, i1), in lexicographic order."""
+    v = _c(v, np.uint8)
+    n_v, ld = v.shape
+    ss = s * s
+    i1 = n_v if i1 is None else min(i1, n_v)
+    i1 = min(i1, max(n_v - 1, 0))
+    if i0 >= i1:
+        return np.zeros((0, ss), np.int64), np.zeros((0, ss), np.float64)
+    npair = pair_index(n_v, i1 - 1, n_v - 1) + 1 - pair_index(n_v, i0, i0 + 1)
+    tables = np.zeros((npair, ss), dtype=np.int64)
+    ccc = np.zeros((npair, ss), dtype=np.float64) if with_ccc else None
+    cnt = multi_counts1(v, n_f, s)
+    _lib().oracle_multi_2way_rows(v.ctypes.data, n_v, n_f, ld, s, i0, i1, cnt.ctypes.data, gamma,
+                                  tables.ctypes.data, ccc.ctypes.data if with_ccc else None)
+    return tables, ccc
+
+
+def multi_pairs_list(v, n_f, s, ia, jb, gamma=GAMMA):
+    """Tables int64 [np, s*s] and CCC double [np, s*s] of the pairs (ia[p], jb[p])."""
+    v = _c(v, np.uint8)
+    ia = _c(ia, np.int64)
+    jb = _c(jb, np.int64)
+    ss = s * s
+    tables = np.zeros((len(ia), ss), dtype=np.int64)
+    ccc = np.zeros((len(ia), ss), dtype=np.float64)
+    cnt = multi_counts1(v, n_f, s)
+    if len(ia):
+        _lib().oracle_multi_2way_list(v.ctypes.data, v.shape[1], n_f, s, ia.ctypes.data,
+                                      jb.ctypes.data, len(ia), cnt.ctypes.data, gamma,
+                                      tables.ctypes.data, ccc.ctypes.data)
+    return tables, ccc
+
+
+def multi_fp2_from_input(v, n_f, s, w, u) -> np.ndarray:
+    v = _c(v, np.uint8)
+    out = np.zeros(s * s, dtype=np.uint64)
+    _lib().oracle_multi_fp2_from_input(v.ctypes.data, v.shape[0], n_f, v.shape[1], s,
+                                       _c(w, np.uint64).ctypes.data, _c(u, np.uint64).ctypes.data,
+                                       out.ctypes.data)
+    return out
+
+
+def multi_fp2_from_tables(tables, n_v, s, w, u) -> np.ndarray:
+    t = _c(tables, np.int32)
+    out = np.zeros(s * s, dtype=np.uint64)
+    _lib().oracle_multi_fp2_from_tables(t.ctypes.data, n_v, s, _c(w, np.uint64).ctypes.data,
+                                        _c(u, np.uint64).ctypes.data, out.ctypes.data)
+    return out

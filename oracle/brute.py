@@ -141,3 +141,30 @@ def tally3_via_x(codes: np.ndarray, missing_aware: bool = True) -> np.ndarray:
     res = [out[i, j, k].reshape(8) for i in range(n) for j in range(i + 1, n)
            for k in range(j + 1, n)]
     return np.array(res, dtype=np.int64).reshape(-1, 8)
+
+
+# ---------------------------------------------------------------------------
+# Multi-allelic 2-way tallies (the s-state extension of Sec. 7, item 2).
+# ---------------------------------------------------------------------------
+
+def multi_tally2(a1_i, a2_i, a1_j, a2_j, s):
+    """s x s table [a][b] for two vectors given as explicit allele pairs
+    (a1[q], a2[q]), -1 in either marking a missing entry: every allele of one
+    entry is paired with every allele of the other and the pair of states is
+    tallied, as in the 2-way worked example of Sec. 2.1."""
+    t = np.zeros((s, s), dtype=np.int64)
+    for x1, x2, y1, y2 in zip(a1_i, a2_i, a1_j, a2_j):
+        if min(x1, x2, y1, y2) < 0:
+            continue
+        for x in (x1, x2):
+            for y in (y1, y2):
+                t[x, y] += 1
+    return t
+
+
+def multi_all_pairs(a1, a2, s):
+    """[P, s*s] tables for all i<j in lexicographic order, entry a*s + b."""
+    n = a1.shape[0]
+    out = [multi_tally2(a1[i], a2[i], a1[j], a2[j], s).reshape(s * s)
+           for i in range(n) for j in range(i + 1, n)]
+    return np.array(out, dtype=np.int64).reshape(-1, s * s)

@@ -542,6 +542,186 @@ void oracle_fp3_from_tables(const int32_t* tables, int64_t n_v, int64_t t_begin,
 }
 
 /* Threads an OpenMP region would use (1 without OpenMP). */
+/* ========================================================================= */
+/* Multi-allelic 2-way CCC: markers with s states (2 <= s <= 4).  The paper    */
+/* states this extension (Sec. 7, item 2): a pair of markers with s1 and s2   */
+/* states gets the s1 x s2 table of relationships.  The 2-way definitions of  */
+/* Sec. 2.1 are taken over the state set {0, .., s-1} unchanged:              */
+/*   rho_{i,q}(a) = copies of state a among the entry's two alleles,          */
+/*   f_i(a) = n_i(a) / (2 m_i),  C_ij(a,b) = sum_q rho_i(a) rho_j(b),          */
+/*   f_ij(a,b) = C_ij(a,b) / (4 m_ij),                                        */
+/*   CCC_ij(a,b) = f_ij(a,b) (1 - g f_i(a)) (1 - g f_j(b)),                    */
+/* with the same missing-data readings as above.  A marker with fewer than s  */
+/* states simply never holds the others (zero rows / columns).                */
+/*                                                                             */
+/* Input: uint8 v[n][ld], one byte per field: bits 2a, 2a+1 hold rho(a) for    */
+/* a < s.  A present entry has counts summing to 2; the byte 0 is a missing   */
+/* entry.  Tables and CCC hold s*s entries per pair, entry a*s + b.           */
+/* ========================================================================= */
+
+static inline int mrho(uint8_t byte, int a) { return (byte >> (2 * a)) & 3; }
+
+/* 1 when the entry holds two alleles among the first s states. */
+static inline int mpresent(uint8_t byte, int s) {
+  int total = 0;
+  for (int a = 0; a < s; ++a) total += mrho(byte, a);
+  return total == 2;
+}
+
+/* Number of bytes among the first n_f of every row that are neither a
+   genotype (counts summing to 2 over the first s states, no other bits) nor
+   the missing byte 0. */
+int64_t oracle_multi_invalid(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s) {
+  int64_t bad = 0;
+  const unsigned high = s >= 4 ? 0u : (0xFFu << (2 * s)) & 0xFFu;
+  for (int64_t i = 0; i < n_v; ++i)
+    for (int64_t q = 0; q < n_f; ++q) {
+      uint8_t b = v[i * ld + q];
+      if (b != 0 && (!mpresent(b, s) || (b & high))) ++bad;
+    }
+  return bad;
+}
+
+/* out[i*5 + a] = n_i(a) for a < 4 (0 for a >= s), out[i*5 + 4] = m_i. */
+void oracle_multi_counts1(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s,
+                          int64_t* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n_v; ++i) {
+    int64_t n[4] = {0, 0, 0, 0}, m = 0;
+    for (int64_t q = 0; q < n_f; ++q) {
+      uint8_t b = v[i * ld + q];
+      if (!mpresent(b, s)) continue;
+      ++m;
+      for (int a = 0; a < s; ++a) n[a] += mrho(b, a);
+    }
+    for (int a = 0; a < 4; ++a) out[i * 5 + a] = n[a];
+    out[i * 5 + 4] = m;
+  }
+}
+
+static void multi_tally(const uint8_t* ri, const uint8_t* rj, int64_t n_f, int s,
+                        int64_t* t) {
+  for (int e = 0; e < s * s; ++e) t[e] = 0;
+  for (int64_t q = 0; q < n_f; ++q) {
+    uint8_t bi = ri[q], bj = rj[q];
+    if (!mpresent(bi, s) || !mpresent(bj, s)) continue;
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) t[a * s + b] += (int64_t)mrho(bi, a) * mrho(bj, b);
+  }
+}
+
+static void multi_ccc(const int64_t* t, int s, const int64_t* ci, const int64_t* cj,
+                      double gamma, double* out) {
+  int64_t sum = 0;
+  for (int e = 0; e < s * s; ++e) sum += t[e];
+  int64_t m_ij = sum / 4; /* fields where both are present */
+  for (int a = 0; a < s; ++a)
+    for (int b = 0; b < s; ++b) {
+      double val = 0.0;
+      if (m_ij > 0) {
+        double f_ij = (double)t[a * s + b] / (4.0 * (double)m_ij);
+        double fi = freq1(ci[a], ci[4]);
+        double fj = freq1(cj[b], cj[4]);
+        val = f_ij * (1.0 - gamma * fi) * (1.0 - gamma * fj);
+      }
+      out[a * s + b] = val;
+    }
+}
+
+/* All pairs i < j with i0 <= i < i1; tables int64 [.][s*s] and ccc (may be
+   NULL) from the first pair of row i0; counts [n_v][5] from
+   oracle_multi_counts1. */
+void oracle_multi_2way_rows(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s,
+                            int64_t i0, int64_t i1, const int64_t* counts, double gamma,
+                            int64_t* tables, double* ccc) {
+  if (i0 >= i1) return;
+  const int ss = s * s;
+  int64_t base = oracle_pair_index(n_v, i0, i0 + 1);
+  for (int64_t i = i0; i < i1; ++i) {
+#pragma omp parallel for schedule(static)
+    for (int64_t j = i + 1; j < n_v; ++j) {
+      int64_t p = oracle_pair_index(n_v, i, j) - base;
+      multi_tally(v + i * ld, v + j * ld, n_f, s, tables + p * ss);
+      if (ccc) multi_ccc(tables + p * ss, s, counts + i * 5, counts + j * 5, gamma, ccc + p * ss);
+    }
+  }
+}
+
+/* Tables and CCC of the listed pairs (ia[p], jb[p]), p < np. */
+void oracle_multi_2way_list(const uint8_t* v, int64_t ld, int64_t n_f, int s, const int64_t* ia,
+                            const int64_t* jb, int64_t np, const int64_t* counts, double gamma,
+                            int64_t* tables, double* ccc) {
+  const int ss = s * s;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t p = 0; p < np; ++p) {
+    multi_tally(v + ia[p] * ld, v + jb[p] * ld, n_f, s, tables + p * ss);
+    if (ccc)
+      multi_ccc(tables + p * ss, s, counts + ia[p] * 5, counts + jb[p] * 5, gamma, ccc + p * ss);
+  }
+}
+
+/* F(a,b) = sum_{i<j} w_i u_j C_ij(a,b) mod 2^61-1 from the input in
+   O(n_v n_f s^2) (as oracle_fp2_from_input); out[a*s + b]. */
+void oracle_multi_fp2_from_input(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s,
+                                 const uint64_t* w, const uint64_t* u, uint64_t* out) {
+  enum { QB = 256 };
+  const int ss = s * s;
+  uint64_t total[16] = {0};
+  int64_t nblk = (n_f + QB - 1) / QB;
+#pragma omp parallel
+  {
+    uint64_t acc[16] = {0};
+    uint64_t pre[4][QB];
+#pragma omp for schedule(dynamic)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+      int64_t q0 = blk * QB, q1 = q0 + QB < n_f ? q0 + QB : n_f;
+      memset(pre, 0, sizeof(pre));
+      for (int64_t j = 0; j < n_v; ++j) {
+        for (int64_t q = q0; q < q1; ++q) {
+          uint8_t b = v[j * ld + q];
+          if (!mpresent(b, s)) continue;
+          for (int x = 0; x < s; ++x)
+            for (int y = 0; y < s; ++y) {
+              uint64_t uy = mulmod(u[j], (uint64_t)mrho(b, y));
+              acc[x * s + y] = addmod(acc[x * s + y], mulmod(uy, pre[x][q - q0]));
+            }
+          for (int x = 0; x < s; ++x)
+            pre[x][q - q0] = addmod(pre[x][q - q0], mulmod(w[j], (uint64_t)mrho(b, x)));
+        }
+      }
+    }
+#pragma omp critical
+    for (int e = 0; e < ss; ++e) total[e] = addmod(total[e], acc[e]);
+  }
+  for (int e = 0; e < ss; ++e) out[e] = total[e];
+}
+
+/* The same checksum over given int32 tables [pairs][s*s]. */
+void oracle_multi_fp2_from_tables(const int32_t* tables, int64_t n_v, int s, const uint64_t* w,
+                                  const uint64_t* u, uint64_t* out) {
+  const int ss = s * s;
+  uint64_t total[16] = {0};
+#pragma omp parallel
+  {
+    uint64_t acc[16] = {0};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n_v; ++i) {
+      int64_t p = oracle_pair_index(n_v, i, i + 1);
+      for (int64_t j = i + 1; j < n_v; ++j, ++p) {
+        uint64_t wu = mulmod(w[i], u[j]);
+        for (int e = 0; e < ss; ++e) {
+          int64_t t = tables[p * ss + e];
+          uint64_t tv = t >= 0 ? (uint64_t)t : P61 - (uint64_t)(-t);
+          acc[e] = addmod(acc[e], mulmod(wu, tv));
+        }
+      }
+    }
+#pragma omp critical
+    for (int e = 0; e < ss; ++e) total[e] = addmod(total[e], acc[e]);
+  }
+  for (int e = 0; e < ss; ++e) out[e] = total[e];
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

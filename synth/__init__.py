@@ -64,8 +64,9 @@ def _lib():
         lib.synth_weights.argtypes = [ptr, i64, u64, u64]
         lib.synth_beta_half.argtypes = [u64, i64]
         lib.synth_beta_half.restype = dbl
+        lib.synth_multi_hw.argtypes = [ptr, i64, i64, i64, cint, u64, dbl, cint]
         for f in (lib.synth_uniform, lib.synth_beta_hw, lib.synth_placement, lib.synth_constant,
-                  lib.synth_batch_sizes, lib.synth_weights):
+                  lib.synth_batch_sizes, lib.synth_weights, lib.synth_multi_hw):
             f.restype = None
         _lib_handle = lib
     return _lib_handle
@@ -148,6 +149,45 @@ def pack_codes(codes: np.ndarray, ld=None, pad_value=0) -> np.ndarray:
     q = full.reshape(n_v, ld, 4).astype(np.uint32)
     packed = q[:, :, 0] | (q[:, :, 1] << 2) | (q[:, :, 2] << 4) | (q[:, :, 3] << 6)
     return packed.astype(np.uint8)
+
+
+def ld_multi(n_f: int, extra: int = 0) -> int:
+    """Smallest legal row stride of the one-byte multi-allelic layout (a
+    multiple of 16 bytes, at least 16), plus ``extra`` 16-byte units."""
+    return (max(1, (n_f + 15) // 16) + extra) * 16
+
+
+def multi_hw(n_v, n_f, s, seed=0, missing=0.0, ld=None, pad="garbage") -> np.ndarray:
+    """Multi-allelic genotypes with ``s`` (2..4) states per marker in the
+    one-byte count layout (bits 2a..2a+1 = copies of state a; 0 = missing):
+    per-vector frequencies from normalised sin^2 weights, Hardy-Weinberg
+    pairs, then missing with probability ``missing``."""
+    if not 2 <= s <= 4:
+        raise ValueError("s must be 2, 3 or 4")
+    ld = ld_multi(n_f) if ld is None else ld
+    v = _alloc(n_v, ld)
+    if n_v:
+        _lib().synth_multi_hw(v.ctypes.data, n_v, n_f, ld, s, seed, missing, _pad(pad))
+    return v
+
+
+def pack_alleles(a1: np.ndarray, a2: np.ndarray, ld=None, pad="garbage") -> np.ndarray:
+    """One-byte count layout from explicit ``[n_v, n_f]`` allele indices (the
+    two alleles of each entry, values 0..3; -1 in either marks a missing
+    entry)."""
+    a1 = np.asarray(a1, dtype=np.int64)
+    a2 = np.asarray(a2, dtype=np.int64)
+    n_v, n_f = a1.shape
+    ld = ld_multi(n_f) if ld is None else ld
+    out = np.zeros((n_v, ld), dtype=np.uint8)
+    if pad == "garbage":
+        out[:] = np.random.default_rng(4321).integers(0, 256, size=out.shape, dtype=np.uint8)
+    else:
+        out[:] = 0
+    miss = (a1 < 0) | (a2 < 0)
+    byte = (np.left_shift(1, 2 * np.clip(a1, 0, 3)) + np.left_shift(1, 2 * np.clip(a2, 0, 3)))
+    out[:, :n_f] = np.where(miss, 0, byte).astype(np.uint8)
+    return out
 
 
 def batch_sizes(n_probs, seed=0, v_lo=256, v_hi=8192, f_lo=1000, f_hi=50000):

@@ -45,7 +45,8 @@ static inline double u53(uint64_t h) { return (double)(h >> 11) * (1.0 / 9007199
 /* Uniform double in [0,1) from the low 32 bits (independent of u53's bits). */
 static inline double u32lo(uint64_t h) { return (double)(h & 0xFFFFFFFFull) * (1.0 / 4294967296.0); }
 
-enum { TAG_P = 1, TAG_G = 2, TAG_PAD = 3, TAG_SIZE = 4, TAG_W = 5 };
+enum { TAG_P = 1, TAG_G = 2, TAG_PAD = 3, TAG_SIZE = 4, TAG_W = 5, TAG_MP = 6, TAG_MG = 7,
+       TAG_MG2 = 8 };
 
 static inline void put_code(uint8_t* row, int64_t q, unsigned code) {
   uint8_t* b = row + (q >> 2);
@@ -171,4 +172,41 @@ void synth_batch_sizes(int64_t n_probs, uint64_t seed, int64_t v_lo, int64_t v_h
 void synth_weights(uint64_t* w, int64_t n, uint64_t seed, uint64_t tag) {
   const uint64_t P61 = (1ull << 61) - 1;
   for (int64_t i = 0; i < n; ++i) w[i] = ctr_hash(seed, TAG_W + tag, (uint64_t)i, 7) % P61;
+}
+
+/*
+ * Multi-allelic genotypes in the one-byte count layout: one byte per field,
+ * `ld` bytes per row; bits 2a and 2a+1 of the byte hold how many of the
+ * entry's two alleles are state a (a < s <= 4), and a missing entry is the
+ * byte 0.  Per vector, state weights sin^2(pi u_a / 2) (u_a uniform) are
+ * normalised into allele frequencies; the two alleles of an entry are
+ * independent draws from them (Hardy-Weinberg); then the entry is replaced by
+ * the missing byte with probability `missing`.  Bytes past n_f are padding
+ * (zero, or random garbage with pad_mode 1).
+ */
+void synth_multi_hw(uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s, uint64_t seed,
+                    double missing, int pad_mode) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n_v; ++i) {
+    uint8_t* row = v + i * ld;
+    double cdf[4] = {0.0, 0.0, 0.0, 0.0}, tot = 0.0;
+    for (int a = 0; a < s; ++a) {
+      double sn = sin(1.5707963267948966 * u53(ctr_hash(seed, TAG_MP, (uint64_t)i, (uint64_t)a)));
+      tot += sn * sn + 1e-3;
+      cdf[a] = tot;
+    }
+    for (int64_t q = 0; q < n_f; ++q) {
+      uint64_t h1 = ctr_hash(seed, TAG_MG, (uint64_t)i, (uint64_t)q);
+      uint64_t h2 = ctr_hash(seed, TAG_MG2, (uint64_t)i, (uint64_t)q);
+      double x1 = u53(h1) * tot, x2 = u53(h2) * tot;
+      int a1 = 0, a2 = 0;
+      while (a1 < s - 1 && x1 >= cdf[a1]) ++a1;
+      while (a2 < s - 1 && x2 >= cdf[a2]) ++a2;
+      unsigned byte = (1u << (2 * a1)) + (1u << (2 * a2));
+      if (missing > 0.0 && u32lo(h2) < missing) byte = 0u;
+      row[q] = (uint8_t)byte;
+    }
+    for (int64_t q = n_f; q < ld; ++q)
+      row[q] = pad_mode == 1 ? (uint8_t)ctr_hash(seed, TAG_PAD, (uint64_t)i, (uint64_t)q) : 0;
+  }
 }

@@ -107,7 +107,51 @@ static int run(int64_t n, int64_t n_f, int64_t ld) {
   return 0;
 }
 
+/* Multi-allelic entry points on random bytes (valid genotypes, missing bytes
+   and arbitrary bytes alike) with s = 2..4 states. */
+static int run_multi(int64_t n, int64_t n_f, int64_t ld, int s) {
+  uint8_t* v = malloc((size_t)(n * ld));
+  for (int64_t i = 0; i < n * ld; ++i) v[i] = (uint8_t)next();
+  (void)oracle_multi_invalid(v, n, n_f, ld, s);
+  int64_t* cnt = malloc(sizeof(int64_t) * 5 * n);
+  oracle_multi_counts1(v, n, n_f, ld, s, cnt);
+  const int ss = s * s;
+  int64_t np = n * (n - 1) / 2;
+  int64_t* t = malloc(sizeof(int64_t) * ss * (np ? np : 1));
+  double* c = malloc(sizeof(double) * ss * (np ? np : 1));
+  int32_t* ti = malloc(sizeof(int32_t) * ss * (np ? np : 1));
+  if (n >= 2) oracle_multi_2way_rows(v, n, n_f, ld, s, 0, n - 1, cnt, 2.0 / 3.0, t, c);
+  for (int64_t p = 0; p < np; ++p) {
+    int64_t sum = 0;
+    for (int e = 0; e < ss; ++e) {
+      sum += t[p * ss + e];
+      CHECK(c[p * ss + e] >= 0.0 && c[p * ss + e] <= 1.0);
+      ti[p * ss + e] = (int32_t)t[p * ss + e];
+    }
+    CHECK(sum % 4 == 0 && sum <= 4 * n_f);
+  }
+  int64_t ia[4] = {0, 0, n - 1, n / 2}, jb[4] = {n - 1, 0, 0, n / 2};
+  int64_t tl[4 * 16];
+  double cl[4 * 16];
+  oracle_multi_2way_list(v, ld, n_f, s, ia, jb, 4, cnt, 2.0 / 3.0, tl, cl);
+  uint64_t* w = malloc(sizeof(uint64_t) * 2 * n);
+  for (int64_t i = 0; i < 2 * n; ++i) w[i] = next() % P61;
+  uint64_t fa[16], fb[16];
+  oracle_multi_fp2_from_input(v, n, n_f, ld, s, w, w + n, fa);
+  oracle_multi_fp2_from_tables(ti, n, s, w, w + n, fb);
+  for (int e = 0; e < ss; ++e) CHECK(fa[e] == fb[e]);
+  free(v); free(cnt); free(t); free(c); free(ti); free(w);
+  return 0;
+}
+
 int main(void) {
+  const int64_t mshapes[][3] = {{2, 1, 16}, {3, 17, 32}, {8, 100, 112}, {11, 0, 16}};
+  for (size_t k = 0; k < sizeof(mshapes) / sizeof(mshapes[0]); ++k)
+    for (int s = 2; s <= 4; ++s)
+      if (run_multi(mshapes[k][0], mshapes[k][1], mshapes[k][2], s)) {
+        fprintf(stderr, "multi shape %zu s %d failed\n", k, s);
+        return 1;
+      }
   const int64_t shapes[][3] = {{2, 1, 16}, {3, 5, 16}, {7, 65, 32}, {12, 257, 80}, {5, 0, 16},
                                {9, 300, 96}};
   for (size_t s = 0; s < sizeof(shapes) / sizeof(shapes[0]); ++s) {

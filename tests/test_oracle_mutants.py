@@ -2,7 +2,8 @@
 
 Each case copies oracle/ccc_oracle.c, plants one plausible mistake (a dropped
 term, a wrong index or sign, a swapped operand, a wrong normaliser), builds it
-on the CPU and runs the pin suite against it in a subprocess: at least one pin
+on the CPU and runs the pin suites (biallelic and multi-allelic) against it in
+a subprocess: at least one pin
 must fail for every mutant, and the unmodified copy must pass.  The oracle
 sources are not modified.
 """
@@ -47,9 +48,23 @@ MUTANTS = [
     ("counts miss the n(1) term", "n1 += rho(c, 1);", "n1 += rho(c, 0);"),
     ("checksum prefix excludes w", "pre[a][q - q0] = addmod(pre[a][q - q0], mulmod(w[j], (uint64_t)rho(c, a)));",
      "pre[a][q - q0] = addmod(pre[a][q - q0], mulmod(u[j], (uint64_t)rho(c, a)));"),
+    # multi-allelic section
+    ("multi state field shift", "return (byte >> (2 * a)) & 3;", "return (byte >> a) & 3;"),
+    ("multi one copy counts as present", "return total == 2;", "return total >= 1;"),
+    ("multi table order b,a", "t[a * s + b] += (int64_t)mrho(bi, a) * mrho(bj, b);",
+     "t[b * s + a] += (int64_t)mrho(bi, a) * mrho(bj, b);"),
+    ("multi f_j normaliser index", "double fj = freq1(cj[b], cj[4]);",
+     "double fj = freq1(cj[b], cj[3]);"),
+    ("multi m_ij from sum/2", "for (int e = 0; e < s * s; ++e) sum += t[e];\n  int64_t m_ij = sum / 4;",
+     "for (int e = 0; e < s * s; ++e) sum += t[e];\n  int64_t m_ij = sum / 2;"),
+    ("multi counts include missing", "if (!mpresent(b, s)) continue;\n      ++m;", "++m;"),
+    ("multi checksum prefix uses u",
+     "pre[x][q - q0] = addmod(pre[x][q - q0], mulmod(w[j], (uint64_t)mrho(b, x)));",
+     "pre[x][q - q0] = addmod(pre[x][q - q0], mulmod(u[j], (uint64_t)mrho(b, x)));"),
 ]
 
-PIN_TESTS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+             os.path.join(ROOT, "tests", "test_oracle_multi_pins.py")]
 
 
 def build_variant(tmp_path, name, find, repl):
@@ -68,7 +83,7 @@ def build_variant(tmp_path, name, find, repl):
 def run_pins(so):
     env = dict(os.environ, CCC_ORACLE_LIB=so, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "-m", "not gpu", PIN_TESTS], cwd=ROOT, env=env, capture_output=True,
+                        "-m", "not gpu", *PIN_TESTS], cwd=ROOT, env=env, capture_output=True,
                        text=True, timeout=600)
     return r.returncode, r.stdout[-400:]
 
