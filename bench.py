@@ -15,7 +15,7 @@ Other workloads (--config): c1 (2-way 512 x 1000, popcount path), c2c (the
 c2 shape with no missing entries: the complete-data path), c3 (3-way
 2048 x 16384), c3c (the c3 shape with no missing entries), c4 (64 batched
 2-way problems), c5 (2-way off-diagonal block 16384 x 16384 over 131072
-fields in 8 chunks).
+fields in 8 chunks), c2m (multi-allelic 2-way, 16384 x 32768, 4 states).
 """
 from __future__ import annotations
 
@@ -249,6 +249,53 @@ def bench_3way(args, lib, missing, workload):
     return out
 
 
+def bench_multi(args, lib):
+    import torch
+    import paper_1705_08213_amd as ccc
+    import synth
+    n_v, n_f, s, missing = 16384, 32768, 4, 0.01
+    log(f"generating {n_v} x {n_f} multi-allelic input, s = {s}")
+    v = synth.multi_hw(n_v, n_f, s, seed=0, missing=missing)
+    dv = torch.from_numpy(v).cuda()
+    P = ccc.n_pairs(n_v)
+    tables = torch.empty((P, s * s), dtype=torch.int32, device="cuda")
+    cc = torch.empty((P, s * s), dtype=torch.float64, device="cuda")
+    counts = torch.empty((n_v, 8), dtype=torch.int32, device="cuda")
+
+    def step():
+        ccc.ccc_2way_multi(dv, n_f, s, tables, cc, counts)
+
+    ms, kms, _ = timed(step, args.steps, args.warmup, lib, "multi2")
+    comps = P * n_f
+    ops = 2.0 * s * s * comps  # s^2 int8 MACs per comparison
+    ach = ops / (kms / 1e3) / 1e12
+    out = dict(metric="CCC comparisons/sec (pairs*n_f), bit-exact tables", value=comps / (ms / 1e3),
+               unit="comparisons/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="i8", data="synthetic",
+               config=dict(workload=f"2-way multi-allelic CCC: n_v={n_v} x n_f={n_f}, s={s} "
+                                    "states, normalised sin^2 frequencies / Hardy-Weinberg, "
+                                    "1% missing", n_v=n_v, n_f=n_f, states=s, missing=missing,
+                           path="mfma"),
+               roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
+                             frac=ach / INT8_PEAK_TOPS, traffic=None,
+                             algorithmic_bytes=n_v * n_f + P * s * s * 12 + 32 * n_v,
+                             kernel="multi2_kernel", kernel_ms=kms,
+                             int8_ops_per_comparison=int(2 * s * s)))
+    if not args.no_cpu:
+        import oracle
+        rows = args.cpu_rows
+        t0 = time.perf_counter()
+        oracle.multi_two_way(v, n_f, s, 0, rows)
+        dt = time.perf_counter() - t0
+        pairs = sum(n_v - 1 - i for i in range(rows))
+        out["cpu_baseline"] = dict(value=pairs * n_f / dt, unit="comparisons/s",
+                                   cores=oracle.num_threads(), kind="oracle",
+                                   sample=f"rows i in [0,{rows}) x all j>i of the same input "
+                                          f"({pairs} pairs x {n_f} fields, {dt:.1f} s)")
+    return out
+
+
 def bench_block(args, lib):
     import torch
     import paper_1705_08213_amd as ccc
@@ -323,7 +370,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pop-steps", type=int, default=2, help="popcount-path steps (c2)")
     ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c2c", "c3", "c3c", "c4", "c5"])
+                    choices=["c1", "c2", "c2c", "c2m", "c3", "c3c", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=8)
     ap.add_argument("--select-threshold", type=float, default=None,
@@ -372,6 +419,8 @@ def main():
                                          "Beta(0.5,0.5)/Hardy-Weinberg, no missing")
     elif args.config == "c4":
         out = bench_many(args, lib)
+    elif args.config == "c2m":
+        out = bench_multi(args, lib)
     else:
         out = bench_block(args, lib)
     print(json.dumps(out), flush=True)

@@ -213,6 +213,34 @@ typedef struct {
 int ccc_2way_many(const ccc_problem* probs, int n_probs, const ccc_opts* opts,
                   hipStream_t stream);
 
+/*
+ * ccc_2way_multi -- multi-allelic 2-way CCC: markers with s = 2..4 states,
+ * an s x s table per pair (the extension announced in Sec. 7 item 2: for
+ * markers with s1 and s2 states, the s1 x s2 table of relationships).  The
+ * Sec. 2.1 definitions are taken over the states {0, .., s-1}:
+ *   rho_{i,q}(a) = copies of state a among entry (i,q)'s two alleles,
+ *   f_i(a) = n_i(a) / (2 m_i),  C_ij(a,b) = sum_q rho_i(a) rho_j(b),
+ *   CCC_ij(a,b) = C_ij(a,b)/(4 m_ij) * (1 - gamma f_i(a)) (1 - gamma f_j(b)),
+ * with the missing-data rules of ccc_2way.
+ *   v       [n_v][ld] one byte per field (ld >= n_f, ld % 16 == 0): bits 2a
+ *           and 2a+1 hold rho(a) for a < s.  A genotype's counts sum to 2; the
+ *           byte 0 is a missing entry.  Other byte values are invalid input:
+ *           the outputs for them are unspecified (nothing is read or written
+ *           out of bounds).  Bytes past n_f are ignored.  A marker with fewer
+ *           than s states leaves its other rows and columns zero.
+ *   s       states, 2 <= s <= 4 (else CCC_ERR_ARG).
+ *   tables  int32 [n_v(n_v-1)/2][s*s] or NULL, entry a*s + b; written.
+ *   ccc     double [n_v(n_v-1)/2][s*s] or NULL; at least one of the two.
+ *   counts  int32 [n_v][8] or NULL: (n(0), n(1), n(2), n(3), m, 0, 0, 0),
+ *           n(a) = 0 for a >= s.
+ * Pairs are in lexicographic order p(i,j).  opts: path AUTO or MFMA (there is
+ * no popcount form: CCC_ERR_UNSUPPORTED), flags 0.  CCC_ERR_RANGE if
+ * 4*n_f > INT32_MAX.  Pointers 16-byte aligned (CCC_ERR_ALIGN).
+ */
+int ccc_2way_multi(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s,
+                   int32_t* tables, double* ccc, int32_t* counts, const ccc_opts* opts,
+                   hipStream_t stream);
+
 /* Static text for a status code. */
 const char* ccc_status_string(int status);
 
@@ -222,7 +250,8 @@ void ccc_release_workspace(void);
 /*
  * Kernel timing (profiling aid, off by default).  While enabled, the library
  * records a pair of HIP events on the launching stream around each tally
- * kernel launch; names are "count1", "pop2", "mfma2", "pop3", "mfma3".
+ * kernel launch; names are "count1", "pop2", "mfma2", "pop3", "mfma3",
+ * "multi2".
  * Do not enable it while a stream is being captured into a graph.
  *   ccc_timing_query: total milliseconds and number of recorded launches of
  *   kernel `name` (NULL = all); waits for the recorded events.

@@ -69,11 +69,12 @@ def lib():
         L.ccc_2way_many.argtypes = [ctypes.POINTER(ccc_problem), cint, opts_p, vp]
         L.ccc_2way_rows.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp, vp, opts_p, vp]
         L.ccc_3way_rows.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp, vp, opts_p, vp]
+        L.ccc_2way_multi.argtypes = [vp, i64, i64, i64, cint, vp, vp, vp, opts_p, vp]
         sel_p = ctypes.POINTER(ccc_selection)
         L.ccc_2way_select.argtypes = [vp, i64, i64, i64, ctypes.c_double, sel_p, vp, opts_p, vp]
         L.ccc_3way_select.argtypes = [vp, i64, i64, i64, ctypes.c_double, sel_p, vp, opts_p, vp]
         for f in (L.ccc_2way, L.ccc_3way, L.ccc_2way_block, L.ccc_2way_many, L.ccc_2way_rows,
-                  L.ccc_3way_rows, L.ccc_2way_select, L.ccc_3way_select):
+                  L.ccc_3way_rows, L.ccc_2way_select, L.ccc_3way_select, L.ccc_2way_multi):
             f.restype = cint
         L.ccc_timing_enable.argtypes = [cint]
         L.ccc_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(cint)]
@@ -182,6 +183,33 @@ def ccc_2way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMM
     st = lib().ccc_2way(_ptr(v), n_v, n_f, ld, _ptr(tables), _ptr(ccc), _ptr(counts),
                         ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_2way")
+    return tables, ccc, counts
+
+
+def ccc_2way_multi(v, n_f, s, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
+                   want_tables=True, want_ccc=True, stream=None):
+    """Multi-allelic pairs i<j over s = 2..4 states (one byte per field, bits
+    2a..2a+1 = copies of state a, 0 = missing): returns (tables int32 [P, s*s],
+    ccc float64 [P, s*s], counts int32 [n_v, 8])."""
+    torch = _torch()
+    _check_input(v)
+    n_v, ld = v.shape
+    P = n_pairs(n_v)
+    ss = s * s
+    dev = v.device
+    if tables is None and want_tables:
+        tables = torch.empty((P, ss), dtype=torch.int32, device=dev)
+    if ccc is None and want_ccc:
+        ccc = torch.empty((P, ss), dtype=torch.float64, device=dev)
+    if counts is None:
+        counts = torch.empty((n_v, 8), dtype=torch.int32, device=dev)
+    _check_out(tables, (P, ss), torch.int32, "tables")
+    _check_out(ccc, (P, ss), torch.float64, "ccc")
+    _check_out(counts, (n_v, 8), torch.int32, "counts")
+    o = make_opts(path, gamma)
+    st = lib().ccc_2way_multi(_ptr(v), n_v, n_f, ld, s, _ptr(tables), _ptr(ccc), _ptr(counts),
+                              ctypes.byref(o), _stream(stream))
+    _raise(st, "ccc_2way_multi")
     return tables, ccc, counts
 
 

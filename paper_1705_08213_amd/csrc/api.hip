@@ -337,6 +337,37 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   return ccc::run_pair2(a, o.path, stream);
 }
 
+int ccc_2way_multi(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s,
+                   int32_t* tables, double* ccc, int32_t* counts, const ccc_opts* opts,
+                   hipStream_t stream) {
+  ccc_opts o;
+  int st = resolve_opts(opts, &o);
+  if (st) return st;
+  if (o.flags != 0) return CCC_ERR_ARG;
+  if (o.path == CCC_PATH_POPCOUNT) return CCC_ERR_UNSUPPORTED;
+  if (s < 2 || s > 4) return CCC_ERR_ARG;
+  if (n_v < 0 || n_f < 0 || ld < 0 || n_v > kInt32Max) return CCC_ERR_ARG;
+  if (ld % 16 != 0) return CCC_ERR_ALIGN;
+  if (ld < n_f) return CCC_ERR_ARG;
+  if (n_v > 0 && !v) return CCC_ERR_ARG;
+  if (!aligned16(v) || !aligned16(tables) || !aligned16(ccc) || !aligned16(counts))
+    return CCC_ERR_ALIGN;
+  if (4 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  if (n_v >= 2 && !tables && !ccc) return CCC_ERR_ARG;
+  if (n_v == 0 || (n_v == 1 && !counts)) return CCC_OK;
+  int32_t* cnt = counts;
+  if (!cnt) {
+    void* ws = nullptr;
+    if ((st = ccc::workspace((size_t)n_v * 32, &ws))) return st;
+    cnt = static_cast<int32_t*>(ws);
+  }
+  if (ccc::launch_multi_count(v, ld, n_v, n_f, s, cnt, stream) != hipSuccess) return CCC_ERR_HIP;
+  if (n_v < 2) return CCC_OK;
+  return ccc::launch_multi2(v, ld, n_v, n_f, s, tables, ccc, cnt, o.gamma, stream) == hipSuccess
+             ? CCC_OK
+             : CCC_ERR_HIP;
+}
+
 int ccc_2way_many(const ccc_problem* probs, int n_probs, const ccc_opts* opts,
                   hipStream_t stream) {
   ccc_opts o;

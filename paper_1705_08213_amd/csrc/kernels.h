@@ -165,5 +165,12 @@ hipError_t launch_pop2(const Pair2Args& a, hipStream_t stream);
 hipError_t launch_mfma2(const Pair2Args& a, hipStream_t stream);
 hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream);
 hipError_t launch_pop3(const Triple3Args& a, hipStream_t stream);
+// Multi-allelic 2-way (one byte per field, s = 2..4 states): counts are
+// [n][8] = (n(0), n(1), n(2), n(3), m, 0, 0, 0); tables / ccc [pairs][s*s].
+hipError_t launch_multi_count(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int s,
+                              int32_t* counts, hipStream_t stream);
+hipError_t launch_multi2(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int s,
+                         int32_t* tables, double* ccc, const int32_t* counts, double gamma,
+                         hipStream_t stream);
 
 }  // namespace ccc

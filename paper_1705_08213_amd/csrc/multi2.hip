@@ -1,0 +1,319 @@
+// multi2.hip -- multi-allelic 2-way tallies and CCC on the int8 matrix cores
+// (markers with s = 2..4 states: the s x s table of relationships of the
+// paper's stated extension, Sec. 7 item 2, with the Sec. 2.1 definitions
+// taken over the state set {0, .., s-1}).
+//
+// Input layout: one byte per field, `ld` bytes per row; bits 2a and 2a+1 of
+// the byte hold rho(a), the copies of state a among the entry's two alleles.
+// A genotype's counts sum to 2; the byte 0 is a missing entry, which gives
+// rho = 0 in every state and so drops out of every tally.  Bytes past n_f
+// are padding and are turned into 0 before use.
+//
+// The tally is s^2 GEMMs C(a,b) = R_a R_b^T over one int8 plane per state,
+// R_a[i][q] = rho_{i,q}(a).  A lane of the 16x16x64 operand holds 16 k-values
+// of one row; here they are the row's 16 bytes at 16 g of each 64-field
+// step, and state a's plane of 4 fields is (w >> 2a) & 0x03030303: one or
+// two VALU ops, no table lookup.  A wave owns (16 WM) x (16 WN) pairs with
+// s^2 accumulator sets; WM, WN are chosen per s to keep the accumulators at
+// 128-144 registers (s = 2: 4 x 2, s = 3: 2 x 2, s = 4: 2 x 1), two waves per
+// SIMD.  Workgroups of 2 x 2 waves cover (32 WM) x (32 WN); the triangle is
+// walked in (32 WM)-square tiles split into WM / WN column parts.
+//
+// Epilogue: m_ij = sum_ab C(a,b) / 4; CCC(a,b) = C/(4 m_ij) * w_i(a) * w_j(b)
+// with the per-vector factors w(a) = 1 - gamma n(a)/(2m) computed once per
+// row and column, and the quotient corrected to the rounded C/(4 m_ij).
+#include "common.h"
+#include "kernels.h"
+
+namespace ccc {
+
+namespace {
+
+constexpr unsigned kLow2 = 0x03030303u;
+
+// Counts row of the multi-allelic layout: (n(0), n(1), n(2), n(3), m, 0, 0, 0).
+constexpr int kMultiCountStride = 8;
+
+// 16 bytes (16 fields) of a row at byte offset ob (a multiple of 16); bytes
+// at or past n_f come back as 0 (missing), and a piece wholly past n_f is
+// not read, so a row is never read past n_f rounded up to 16 bytes.
+__device__ __forceinline__ u4 load_bytes16(const uint8_t* __restrict__ row, int64_t ob,
+                                           int64_t n_f) {
+  u4 w = u4{0u, 0u, 0u, 0u};
+  if (ob >= n_f) return w;
+  w = *reinterpret_cast<const u4*>(row + ob);
+  if (ob + 16 > n_f) {
+    const int64_t valid = n_f - ob;  // 1..15 bytes
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t vb = valid - 4 * t;
+      const unsigned keep = vb >= 4 ? 0xFFFFFFFFu : (vb <= 0 ? 0u : (1u << (8 * vb)) - 1u);
+      w[t] &= keep;
+    }
+  }
+  return w;
+}
+
+// State a's int8 plane of 16 fields.
+__device__ __forceinline__ v4i state_plane(const u4& w, int a) {
+  return v4i{(int)((w.x >> (2 * a)) & kLow2), (int)((w.y >> (2 * a)) & kLow2),
+             (int)((w.z >> (2 * a)) & kLow2), (int)((w.w >> (2 * a)) & kLow2)};
+}
+
+// Sum of the 4 bytes of x when each is at most 63.
+__device__ __forceinline__ unsigned byte_sum(unsigned x) { return (x * 0x01010101u) >> 24; }
+
+// 1-way counts: one wave per row, 16-byte pieces with a 1 KiB lane stride.
+// m = (sum of the state counts) / 2, the present fields of a valid row.
+__global__ __launch_bounds__(256) void multi_count_kernel(const uint8_t* __restrict__ v,
+                                                          int64_t ld, int64_t n, int64_t n_f,
+                                                          int s, int32_t* __restrict__ counts) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int lane = threadIdx.x & 63;
+  const uint8_t* r = v + row * ld;
+  unsigned c[4] = {0u, 0u, 0u, 0u};
+  for (int64_t ob = (int64_t)lane * 16; ob < n_f; ob += 64 * 16) {
+    const u4 w = load_bytes16(r, ob, n_f);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (a < s) {
+        c[a] += byte_sum((w.x >> (2 * a)) & kLow2) + byte_sum((w.y >> (2 * a)) & kLow2) +
+                byte_sum((w.z >> (2 * a)) & kLow2) + byte_sum((w.w >> (2 * a)) & kLow2);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) c[a] += __shfl_xor(c[a], off);
+  if (lane == 0) {
+    v4i* o = reinterpret_cast<v4i*>(counts + kMultiCountStride * row);
+    o[0] = v4i{(int)c[0], (int)c[1], (int)c[2], (int)c[3]};
+    o[1] = v4i{(int)((c[0] + c[1] + c[2] + c[3]) >> 1), 0, 0, 0};
+  }
+}
+
+struct Multi2Args {
+  const uint8_t* v;
+  int64_t ld, n, n_f;
+  int32_t* tables;  // [pairs][S*S] or null
+  double* ccc;      // [pairs][S*S] or null
+  const int32_t* counts;
+  double gamma;
+};
+
+// Factors w(a) = 1 - gamma n(a)/(2m) of row x (clamped into range).
+template <int S>
+__device__ __forceinline__ void multi_factors(const Multi2Args& a, int64_t x, double (&w)[S]) {
+  const int32_t* c = a.counts + kMultiCountStride * (x < a.n ? x : a.n - 1);
+#pragma unroll
+  for (int s = 0; s < S; ++s) w[s] = one_minus_gf(c[s], c[4], a.gamma);
+}
+
+// Store the table t and its CCC at pair p.
+template <int S>
+__device__ __forceinline__ void multi_store(const Multi2Args& a, int64_t p,
+                                            const int (&t)[S * S], const double (&wi)[S],
+                                            const double (&wj)[S]) {
+#pragma clang fp contract(off)
+  constexpr int SS = S * S;
+  if (a.tables) {
+    int32_t* o = a.tables + SS * p;
+    if constexpr (SS % 4 == 0) {
+#pragma unroll
+      for (int x = 0; x < SS; x += 4)
+        *reinterpret_cast<v4i*>(o + x) = v4i{t[x], t[x + 1], t[x + 2], t[x + 3]};
+    } else {
+#pragma unroll
+      for (int x = 0; x < SS; ++x) o[x] = t[x];
+    }
+  }
+  if (a.ccc) {
+    int sum = 0;
+#pragma unroll
+    for (int x = 0; x < SS; ++x) sum += t[x];
+    const int m_ij = sum >> 2;  // fields where both are present
+    double r[SS];
+    if (m_ij > 0) {
+      const double den = 4.0 * (double)m_ij, y = 1.0 / den;
+#pragma unroll
+      for (int x = 0; x < SS; ++x)
+        r[x] = quot_rn((double)t[x], den, y) * wi[x / S] * wj[x % S];
+    } else {
+#pragma unroll
+      for (int x = 0; x < SS; ++x) r[x] = 0.0;
+    }
+    double* o = a.ccc + SS * p;
+    if constexpr (SS % 2 == 0) {
+#pragma unroll
+      for (int x = 0; x < SS; x += 2)
+        *reinterpret_cast<double2*>(o + x) = double2{r[x], r[x + 1]};
+    } else {
+#pragma unroll
+      for (int x = 0; x < SS; ++x) o[x] = r[x];
+    }
+  }
+}
+
+template <int S>
+struct MultiShape;
+template <>
+struct MultiShape<2> {
+  static constexpr int WM = 4, WN = 2;
+};
+template <>
+struct MultiShape<3> {
+  static constexpr int WM = 2, WN = 2;
+};
+template <>
+struct MultiShape<4> {
+  static constexpr int WM = 2, WN = 1;
+};
+
+template <int S>
+__global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t tiles_side) {
+  constexpr int WM = MultiShape<S>::WM, WN = MultiShape<S>::WN;
+  constexpr int BM = 32 * WM, BN = 32 * WN, PARTS = BM / BN;
+  static_assert(BM % BN == 0, "square tiles split into whole column parts");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, rl = lane & 15;
+  int64_t sq_i, sq_j;
+  tri_tile(blockIdx.x / PARTS, tiles_side, sq_i, sq_j);
+  const int64_t row0 = sq_i * BM + (wave & 1) * 16 * WM;
+  const int64_t col0 = (sq_j * PARTS + blockIdx.x % PARTS) * BN + (wave >> 1) * 16 * WN;
+  if (row0 >= a.n || col0 >= a.n || row0 >= col0 + 16 * WN - 1) return;  // no pair i < j
+
+  const uint8_t* pa[WM];
+  const uint8_t* pb[WN];
+#pragma unroll
+  for (int m = 0; m < WM; ++m) {
+    const int64_t r = row0 + 16 * m + rl;
+    pa[m] = a.v + (r < a.n ? r : a.n - 1) * a.ld + 16 * g;
+  }
+#pragma unroll
+  for (int n = 0; n < WN; ++n) {
+    const int64_t r = col0 + 16 * n + rl;
+    pb[n] = a.v + (r < a.n ? r : a.n - 1) * a.ld + 16 * g;
+  }
+
+  v4i acc[WM][WN][S * S];
+#pragma unroll
+  for (int m = 0; m < WM; ++m)
+#pragma unroll
+    for (int n = 0; n < WN; ++n)
+#pragma unroll
+      for (int x = 0; x < S * S; ++x) acc[m][n][x] = v4i{0, 0, 0, 0};
+
+  auto step = [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
+    v4i A[WM][S], B[WN][S];
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int s = 0; s < S; ++s) A[m][s] = state_plane(xa[m], s);
+#pragma unroll
+    for (int n = 0; n < WN; ++n)
+#pragma unroll
+      for (int s = 0; s < S; ++s) B[n][s] = state_plane(xb[n], s);
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int n = 0; n < WN; ++n)
+#pragma unroll
+        for (int x = 0; x < S * S; ++x)
+          acc[m][n][x] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[m][x / S], B[n][x % S],
+                                                               acc[m][n][x], 0, 0, 0);
+  };
+
+  // 64-field steps: plain 16-byte loads, one step ahead, while the step is
+  // whole; then one masked step for the tail.
+  const int64_t nfull = a.n_f / 64;
+  u4 ca[WM], cb[WN];
+  if (nfull > 0) {
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = *reinterpret_cast<const u4*>(pa[m]);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = *reinterpret_cast<const u4*>(pb[n]);
+  }
+  for (int64_t st = 0; st < nfull; ++st) {
+    u4 na[WM], nb[WN];
+    if (st + 1 < nfull) {
+#pragma unroll
+      for (int m = 0; m < WM; ++m) na[m] = *reinterpret_cast<const u4*>(pa[m] + (st + 1) * 64);
+#pragma unroll
+      for (int n = 0; n < WN; ++n) nb[n] = *reinterpret_cast<const u4*>(pb[n] + (st + 1) * 64);
+    }
+    step(ca, cb);
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = na[m];
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = nb[n];
+  }
+  if (nfull * 64 < a.n_f) {
+    const int64_t kb = nfull * 64 + 16 * g;
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[m] = load_bytes16(pa[m] - 16 * g, kb, a.n_f);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[n] = load_bytes16(pb[n] - 16 * g, kb, a.n_f);
+    step(ca, cb);
+  }
+
+  // Epilogue: lane holds rows 4g + e of column rl of each 16x16 block.
+  const bool want_w = a.ccc != nullptr;
+#pragma unroll
+  for (int n = 0; n < WN; ++n) {
+    const int64_t j = col0 + 16 * n + rl;
+    double wj[S];
+    if (want_w) multi_factors<S>(a, j, wj);
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = row0 + 16 * m + 4 * g + e;
+        if (!(i < j && j < a.n)) continue;
+        double wi[S];
+        if (want_w) multi_factors<S>(a, i, wi);
+        int t[S * S];
+#pragma unroll
+        for (int x = 0; x < S * S; ++x) t[x] = acc[m][n][x][e];
+        multi_store<S>(a, pair_index(a.n, i, j), t, wi, wj);
+      }
+  }
+}
+
+template <int S>
+hipError_t launch_multi2_s(const Multi2Args& a, hipStream_t stream) {
+  constexpr int BM = 32 * MultiShape<S>::WM, BN = 32 * MultiShape<S>::WN;
+  const int64_t T = (a.n + BM - 1) / BM;
+  const int64_t ntiles = (BM / BN) * (T * (T + 1) / 2);
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  timing_begin("multi2", stream);
+  hipLaunchKernelGGL(multi2_kernel<S>, dim3((unsigned)ntiles), dim3(256), 0, stream, a, T);
+  timing_end(stream);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_multi_count(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int s,
+                              int32_t* counts, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(multi_count_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, v,
+                     ld, n, n_f, s, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi2(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int s,
+                         int32_t* tables, double* ccc, const int32_t* counts, double gamma,
+                         hipStream_t stream) {
+  Multi2Args a{v, ld, n, n_f, tables, ccc, counts, gamma};
+  switch (s) {
+    case 2: return launch_multi2_s<2>(a, stream);
+    case 3: return launch_multi2_s<3>(a, stream);
+    case 4: return launch_multi2_s<4>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ccc

@@ -154,3 +154,31 @@ def test_ranges_without_pairs_need_no_outputs():
     assert L.ccc_2way_rows(FAKE, 10, 100, 32, 9, 10, None, None, None, o, None) == ccc.CCC_OK
     assert L.ccc_3way_rows(FAKE, 10, 100, 32, 8, 10, None, None, None, o, None) == ccc.CCC_OK
     assert L.ccc_2way_rows(FAKE, 10, 100, 32, 8, 10, None, None, None, o, None) == ccc.CCC_ERR_ARG
+
+
+def test_multi_validation():
+    L = ccc.lib()
+
+    def callm(v=FAKE, n_v=10, n_f=100, ld=112, s=3, tables=FAKE, cc=FAKE, counts=None, path=0,
+              flags=0):
+        o = ccc.make_opts(path, flags=flags)
+        return L.ccc_2way_multi(v, n_v, n_f, ld, s, tables, cc, counts, ctypes.byref(o), None)
+
+    assert callm(s=1) == ccc.CCC_ERR_ARG
+    assert callm(s=5) == ccc.CCC_ERR_ARG
+    assert callm(ld=120) == ccc.CCC_ERR_ALIGN
+    assert callm(ld=96) == ccc.CCC_ERR_ARG                 # ld < n_f
+    assert callm(path=ccc.CCC_PATH_POPCOUNT) == ccc.CCC_ERR_UNSUPPORTED
+    assert callm(flags=ccc.CCC_FINALIZE) == ccc.CCC_ERR_ARG
+    assert callm(tables=None, cc=None) == ccc.CCC_ERR_ARG
+    assert callm(v=None) == ccc.CCC_ERR_ARG
+    assert callm(v=FAKE + 8) == ccc.CCC_ERR_ALIGN
+    assert callm(tables=FAKE + 4) == ccc.CCC_ERR_ALIGN
+    assert callm(cc=FAKE + 8) == ccc.CCC_ERR_ALIGN
+    assert callm(counts=FAKE + 4) == ccc.CCC_ERR_ALIGN
+    assert callm(n_v=-1) == ccc.CCC_ERR_ARG
+    big = I32MAX // 4 + 1
+    assert callm(n_f=big, ld=(big + 15) // 16 * 16) == ccc.CCC_ERR_RANGE
+    # empty problems enqueue nothing
+    assert callm(v=None, n_v=0, tables=None, cc=None) == ccc.CCC_OK
+    assert callm(n_v=1, tables=None, cc=None) == ccc.CCC_OK
