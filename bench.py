@@ -57,6 +57,8 @@ def committed_traffic(kernel_sources, profile):
 
 MFMA2_SOURCES = ["paper_1705_08213_amd/csrc/mfma2.hip", "paper_1705_08213_amd/csrc/tile2.h",
                  "paper_1705_08213_amd/csrc/common.h", "paper_1705_08213_amd/csrc/kernels.h"]
+MULTI2_SOURCES = ["paper_1705_08213_amd/csrc/multi2.hip", "paper_1705_08213_amd/csrc/common.h",
+                  "paper_1705_08213_amd/csrc/kernels.h"]
 MFMA3_SOURCES = ["paper_1705_08213_amd/csrc/mfma3.hip", "paper_1705_08213_amd/csrc/tile3.h",
                  "paper_1705_08213_amd/csrc/tile2.h", "paper_1705_08213_amd/csrc/common.h",
                  "paper_1705_08213_amd/csrc/kernels.h"]
@@ -278,7 +280,10 @@ def bench_multi(args, lib):
                                     "1% missing", n_v=n_v, n_f=n_f, states=s, missing=missing,
                            path="mfma"),
                roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                             frac=ach / INT8_PEAK_TOPS, traffic=None,
+                             frac=ach / INT8_PEAK_TOPS,
+                             traffic=committed_traffic(MULTI2_SOURCES,
+                                                       "profiles/multi2_2way_n16384_f32768_s4.md"),
+                             traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                              algorithmic_bytes=n_v * n_f + P * s * s * 12 + 32 * n_v,
                              kernel="multi2_kernel", kernel_ms=kms,
                              int8_ops_per_comparison=int(2 * s * s)))

@@ -13,15 +13,17 @@ __global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tile
   constexpr int BM = 32 * WM, BN = 32 * WN;
   static_assert(BM == 2 * BN, "triangle split assumes BM = 2 BN");
   const int wave = threadIdx.x >> 6;
+  // XCD-contiguous runs of tiles: a run shares its row block in one L2
+  const int64_t b = xcd_unit(blockIdx.x, gridDim.x);
   int64_t I, J;
   if (a.tri) {
     int64_t sq_i, sq_j;
-    tri_tile((blockIdx.x >> 1) + a.sq_offset, tiles_side, sq_i, sq_j);
+    tri_tile((b >> 1) + a.sq_offset, tiles_side, sq_i, sq_j);
     I = sq_i;
-    J = 2 * sq_j + (blockIdx.x & 1);
+    J = 2 * sq_j + (b & 1);
   } else {
-    I = blockIdx.x / tiles_n;
-    J = blockIdx.x % tiles_n;
+    I = b / tiles_n;
+    J = b % tiles_n;
   }
   tile2::mfma2_wave_tile<WM, WN>(a, I * BM + (wave & 1) * 16 * WM, J * BN + (wave >> 1) * 16 * WN);
 }

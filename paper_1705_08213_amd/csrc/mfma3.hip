@@ -93,23 +93,7 @@ __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, in
 #pragma unroll
       for (int e = 0; e < 8; ++e) acc[m][c][e] = v4i{0, 0, 0, 0};
 
-  const int64_t nbytes = (a.n_f + 3) / 4;
-  for (int64_t kb = 0; kb < nbytes; kb += 64) {
-    const bool full = (kb + 64) * 4 <= a.n_f;
-    u4 xa[WI], xk[WK], xj;
-    if (full) {
-#pragma unroll
-      for (int m = 0; m < WI; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + kb);
-#pragma unroll
-      for (int c = 0; c < WK; ++c) xk[c] = *reinterpret_cast<const u4*>(pk[c] + kb);
-      xj = *reinterpret_cast<const u4*>(pj + kb);
-    } else {
-#pragma unroll
-      for (int m = 0; m < WI; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kb + 16 * g, a.n_f);
-#pragma unroll
-      for (int c = 0; c < WK; ++c) xk[c] = load_fields64(pk[c] - 16 * g, kb + 16 * g, a.n_f);
-      xj = load_fields64(pj - 16 * g, kb + 16 * g, a.n_f);
-    }
+  auto body = [&](const u4 (&xa)[WI], const u4 (&xk)[WK], const u4& xj) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       unsigned cj[4], sel0[4], sel1[4];
@@ -157,6 +141,26 @@ __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, in
         }
       }
     }
+  };
+  // Whole 256-field super-steps with plain loads, then the masked tail.
+  const int64_t nfull = a.n_f / 256;
+  for (int64_t st = 0; st < nfull; ++st) {
+    const int64_t kb = st * 64;
+    u4 xa[WI], xk[WK];
+#pragma unroll
+    for (int m = 0; m < WI; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + kb);
+#pragma unroll
+    for (int c = 0; c < WK; ++c) xk[c] = *reinterpret_cast<const u4*>(pk[c] + kb);
+    body(xa, xk, *reinterpret_cast<const u4*>(pj + kb));
+  }
+  if (nfull * 256 < a.n_f) {
+    const int64_t kb = nfull * 64 + 16 * g;
+    u4 xa[WI], xk[WK];
+#pragma unroll
+    for (int m = 0; m < WI; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
+#pragma unroll
+    for (int c = 0; c < WK; ++c) xk[c] = load_fields64(pk[c] - 16 * g, kb, a.n_f);
+    body(xa, xk, load_fields64(pj - 16 * g, kb, a.n_f));
   }
 
   // Epilogue: entry 4a + 2b + c; lane holds rows 4g + e of column rl.

@@ -160,15 +160,15 @@ template <int S>
 struct MultiShape;
 template <>
 struct MultiShape<2> {
-  static constexpr int WM = 4, WN = 2;
+  static constexpr int WM = 4, WN = 2, U = 1;
 };
 template <>
 struct MultiShape<3> {
-  static constexpr int WM = 2, WN = 2;
+  static constexpr int WM = 2, WN = 2, U = 1;
 };
 template <>
 struct MultiShape<4> {
-  static constexpr int WM = 2, WN = 1;
+  static constexpr int WM = 2, WN = 1, U = 2;
 };
 
 template <int S>
@@ -178,10 +178,12 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
   static_assert(BM % BN == 0, "square tiles split into whole column parts");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, rl = lane & 15;
+  // XCD-contiguous runs of tiles: a run shares its row block in one L2
+  const int64_t b = xcd_unit(blockIdx.x, gridDim.x);
   int64_t sq_i, sq_j;
-  tri_tile(blockIdx.x / PARTS, tiles_side, sq_i, sq_j);
+  tri_tile(b / PARTS, tiles_side, sq_i, sq_j);
   const int64_t row0 = sq_i * BM + (wave & 1) * 16 * WM;
-  const int64_t col0 = (sq_j * PARTS + blockIdx.x % PARTS) * BN + (wave >> 1) * 16 * WN;
+  const int64_t col0 = (sq_j * PARTS + b % PARTS) * BN + (wave >> 1) * 16 * WN;
   if (row0 >= a.n || col0 >= a.n || row0 >= col0 + 16 * WN - 1) return;  // no pair i < j
 
   const uint8_t* pa[WM];
@@ -225,37 +227,49 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
                                                                acc[m][n][x], 0, 0, 0);
   };
 
-  // 64-field steps: plain 16-byte loads, one step ahead, while the step is
-  // whole; then one masked step for the tail.
-  const int64_t nfull = a.n_f / 64;
-  u4 ca[WM], cb[WN];
-  if (nfull > 0) {
+  // 64-field steps in groups of U: plain 16-byte loads of the next group are
+  // issued before the current group's MFMAs while the steps are whole; then
+  // the whole steps left over, and one masked step for the tail.
+  constexpr int U = MultiShape<S>::U;
+  const int64_t nfull = a.n_f / 64, ngroups = nfull / U;
+  u4 ca[U][WM], cb[U][WN];
+  auto load_group = [&](int64_t st0, u4 (&xa)[U][WM], u4 (&xb)[U][WN]) {
 #pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = *reinterpret_cast<const u4*>(pa[m]);
+    for (int u = 0; u < U; ++u) {
 #pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = *reinterpret_cast<const u4*>(pb[n]);
-  }
-  for (int64_t st = 0; st < nfull; ++st) {
-    u4 na[WM], nb[WN];
-    if (st + 1 < nfull) {
+      for (int m = 0; m < WM; ++m) xa[u][m] = *reinterpret_cast<const u4*>(pa[m] + (st0 + u) * 64);
 #pragma unroll
-      for (int m = 0; m < WM; ++m) na[m] = *reinterpret_cast<const u4*>(pa[m] + (st + 1) * 64);
-#pragma unroll
-      for (int n = 0; n < WN; ++n) nb[n] = *reinterpret_cast<const u4*>(pb[n] + (st + 1) * 64);
+      for (int n = 0; n < WN; ++n) xb[u][n] = *reinterpret_cast<const u4*>(pb[n] + (st0 + u) * 64);
     }
-    step(ca, cb);
+  };
+  if (ngroups > 0) load_group(0, ca, cb);
+  for (int64_t gr = 0; gr < ngroups; ++gr) {
+    u4 na[U][WM], nb[U][WN];
+    if (gr + 1 < ngroups) load_group((gr + 1) * U, na, nb);
 #pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = na[m];
+    for (int u = 0; u < U; ++u) step(ca[u], cb[u]);
 #pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = nb[n];
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int m = 0; m < WM; ++m) ca[u][m] = na[u][m];
+#pragma unroll
+      for (int n = 0; n < WN; ++n) cb[u][n] = nb[u][n];
+    }
+  }
+  for (int64_t st = ngroups * U; st < nfull; ++st) {
+#pragma unroll
+    for (int m = 0; m < WM; ++m) ca[0][m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) cb[0][n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
+    step(ca[0], cb[0]);
   }
   if (nfull * 64 < a.n_f) {
     const int64_t kb = nfull * 64 + 16 * g;
 #pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = load_bytes16(pa[m] - 16 * g, kb, a.n_f);
+    for (int m = 0; m < WM; ++m) ca[0][m] = load_bytes16(pa[m] - 16 * g, kb, a.n_f);
 #pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = load_bytes16(pb[n] - 16 * g, kb, a.n_f);
-    step(ca, cb);
+    for (int n = 0; n < WN; ++n) cb[0][n] = load_bytes16(pb[n] - 16 * g, kb, a.n_f);
+    step(ca[0], cb[0]);
   }
 
   // Epilogue: lane holds rows 4g + e of column rl of each 16x16 block.

@@ -144,28 +144,24 @@ __device__ __forceinline__ void wave_loop(const uint8_t* const (&pa)[WM],
                                           Step step) {
   const int64_t nfull = n_f / 256;
   const int64_t nbytes = (n_f + 3) / 4;
-  u4 ca[WM], cb[WN];
-  if (nfull > 0) {
+  // Two register sets in turn (no copies): set 0 holds even super-steps,
+  // set 1 odd ones; each is refilled right after its MFMAs are issued.
+  u4 ca[WM], cb[WN], da[WM], db[WN];
+  auto load = [&](int64_t s, u4 (&xa)[WM], u4 (&xb)[WN]) {
 #pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = *reinterpret_cast<const u4*>(pa[m]);
+    for (int m = 0; m < WM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + s * 64);
 #pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = *reinterpret_cast<const u4*>(pb[n]);
-  }
-  for (int64_t s = 0; s < nfull; ++s) {
-    u4 na[WM], nb[WN];
-    const int64_t kn = (s + 1) * 64;
-    if (s + 1 < nfull) {
-#pragma unroll
-      for (int m = 0; m < WM; ++m) na[m] = *reinterpret_cast<const u4*>(pa[m] + kn);
-#pragma unroll
-      for (int n = 0; n < WN; ++n) nb[n] = *reinterpret_cast<const u4*>(pb[n] + kn);
-    }
+    for (int n = 0; n < WN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + s * 64);
+  };
+  if (nfull > 0) load(0, ca, cb);
+  int64_t s = 0;
+  for (; s + 1 < nfull; s += 2) {
+    load(s + 1, da, db);
     step(ca, cb);
-#pragma unroll
-    for (int m = 0; m < WM; ++m) ca[m] = na[m];
-#pragma unroll
-    for (int n = 0; n < WN; ++n) cb[n] = nb[n];
+    if (s + 2 < nfull) load(s + 2, ca, cb);
+    step(da, db);
   }
+  if (s < nfull) step(ca, cb);
   const int64_t kt = nfull * 64;
   if (kt < nbytes) {
     // row pointers already include the lane's 16*g byte offset
