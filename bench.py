@@ -156,8 +156,9 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
         ach = ops / (kms / 1e3) / 1e12
         traffic = None
         if (n_v, n_f) == (32768, 65536):
-            traffic = committed_traffic(MFMA2_SOURCES,
-                                        "profiles/mfma2_2way_n32768_f65536_traffic.md")
+            traffic = committed_traffic(
+                MFMA2_SOURCES, "profiles/mfma2_2way_n32768_f65536_traffic.md" if missing > 0.0
+                else "profiles/mfma2_2way_complete_n32768_f65536.md")
         out["roofline"] = dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
                                frac=ach / INT8_PEAK_TOPS, traffic=traffic,
                                traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",

@@ -25,6 +25,11 @@ __global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tile
     I = b / tiles_n;
     J = b % tiles_n;
   }
+  __shared__ v4i part[4][16][64];
+  if (tile2::workgroup_complete<WM, WN>(a, I * BM, J * BN)) {
+    tile2::mfma2_coop_complete<WM, WN>(a, I * BM, J * BN, part);
+    return;
+  }
   tile2::mfma2_wave_tile<WM, WN>(a, I * BM + (wave & 1) * 16 * WM, J * BN + (wave >> 1) * 16 * WN);
 }
 

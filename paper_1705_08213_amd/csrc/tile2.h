@@ -309,6 +309,149 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
   }
 }
 
+// Complete-data workgroup tile (every one of its rows has all n_f fields
+// present, as the workgroup has voted): the one-plane product C11 of the
+// whole (32 WM) x (32 WN) tile is computed by all four waves together, each
+// over a quarter of the 256-field super-steps.  A wave then holds
+// (2 WM) x (2 WN) 16x16 blocks, so each unpacked operand word feeds 2 WN
+// (A side) or 2 WM (B side) MFMAs: half the unpack per MFMA of the per-wave
+// form, which is bound by that unpack.  The four partial tiles are added
+// through LDS (`part`, 4 x 16 x 64 x 16 bytes) in two halves of 16 blocks;
+// wave w keeps block rows 2w and 2w+1 and finishes their pairs.  Every thread
+// of the workgroup must call it (barriers).
+template <int WM, int WN>
+__device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t I0, int64_t J0,
+                                                    v4i (*part)[16][64]) {
+  constexpr int TM = 2 * WM, TN = 2 * WN;  // 16x16 blocks of the workgroup tile
+  static_assert(TM == 8 && TN == 4, "the LDS halves hold 4 x 4 blocks");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, rl = lane & 15;
+  const uint8_t* pa[TM];
+  const uint8_t* pb[TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m) {
+    const int64_t r = I0 + 16 * m + rl;
+    pa[m] = a.va + (r < a.n_a ? r : a.n_a - 1) * a.lda + 16 * g;
+  }
+#pragma unroll
+  for (int n = 0; n < TN; ++n) {
+    const int64_t r = J0 + 16 * n + rl;
+    pb[n] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
+  }
+  v4i acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int n = 0; n < TN; ++n) acc[m][n] = v4i{0, 0, 0, 0};
+
+  auto body = [&](const u4 (&xa)[TM], const u4 (&xb)[TN]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      v4i b1[TN];
+#pragma unroll
+      for (int n = 0; n < TN; ++n) b1[n] = unpack16_rho1(word_of(xb[n], s));
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+        const v4i a1 = unpack16_rho1(word_of(xa[m], s));
+#pragma unroll
+        for (int n = 0; n < TN; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1[n], acc[m][n], 0, 0, 0);
+      }
+    }
+  };
+  // This wave's super-steps [s_begin, s_end): the whole ones with plain
+  // loads, then the partial one (holding field n_f - 1) if it is in range.
+  const int64_t steps = (a.n_f + 255) / 256, nfull = a.n_f / 256;
+  const int64_t s_begin = steps * wave / 4, s_end = steps * (wave + 1) / 4;
+  const int64_t e_full = s_end < nfull ? s_end : nfull;
+  for (int64_t st = s_begin; st < e_full; ++st) {
+    u4 xa[TM], xb[TN];
+#pragma unroll
+    for (int m = 0; m < TM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
+#pragma unroll
+    for (int n = 0; n < TN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
+    body(xa, xb);
+  }
+  if (nfull >= s_begin && nfull < s_end) {
+    const int64_t kb = nfull * 64 + 16 * g;
+    u4 xa[TM], xb[TN];
+#pragma unroll
+    for (int m = 0; m < TM; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
+#pragma unroll
+    for (int n = 0; n < TN; ++n) xb[n] = load_fields64(pb[n] - 16 * g, kb, a.n_f);
+    body(xa, xb);
+  }
+
+  // Sum the four partial tiles: half h holds block rows 4h..4h+3, owned by
+  // waves 2h and 2h+1 (two block rows each).
+  v4i own[2][TN];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < TN; ++n) part[wave][m * TN + n][lane] = acc[4 * h + m][n];
+    __syncthreads();
+    if ((wave >> 1) == h) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int ml = 2 * (wave & 1) + r;  // block row within the half
+#pragma unroll
+        for (int n = 0; n < TN; ++n)
+          own[r][n] = part[0][ml * TN + n][lane] + part[1][ml * TN + n][lane] +
+                      part[2][ml * TN + n][lane] + part[3][ml * TN + n][lane];
+      }
+    }
+    __syncthreads();
+  }
+
+  // Epilogue over block rows 2w, 2w+1: C10 = 2 n_i(1) - C11, C01 = 2 n_j(1) - C11,
+  // C00 = 4 n_f - 2 n_i(1) - 2 n_j(1) + C11.
+  const int nf4 = (int)(4 * a.n_f);
+#pragma unroll
+  for (int n = 0; n < TN; ++n) {
+    const int64_t j = J0 + 16 * n + rl;
+    double wj[2];
+    side_factors(a, 1, j, wj);
+    const int n1j = reinterpret_cast<const v4i*>(a.counts_b)[j < a.n_b ? j : a.n_b - 1].y;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = I0 + 16 * (2 * wave + r) + 4 * g + e;
+        const int n1i = reinterpret_cast<const v4i*>(a.counts_a)[i < a.n_a ? i : a.n_a - 1].y;
+        double wi[2];
+        side_factors(a, 0, i, wi);
+        const int c11 = own[r][n][e];
+        const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
+        emit_pair(a, valid, i, j,
+                  v4i{nf4 - 2 * n1i - 2 * n1j + c11, 2 * n1j - c11, 2 * n1i - c11, c11}, wi,
+                  wj);
+      }
+  }
+}
+
+// Workgroup vote for mfma2_coop_complete: every row of the (32 WM) x (32 WN)
+// tile at (I0, J0) complete (rows past the end repeat the last row), in a
+// call that does not accumulate (whose counts are this call's own).  Every
+// thread of the workgroup must call it.
+template <int WM, int WN>
+__device__ __forceinline__ bool workgroup_complete(const Pair2Args& a, int64_t I0, int64_t J0) {
+  if (a.accumulate || a.n_f <= 0) return false;  // uniform: no vote needed
+  const int t = threadIdx.x;
+  bool ok = true;
+  if (t < 32 * WM) {
+    int64_t r = I0 + t;
+    r = r < a.n_a ? r : a.n_a - 1;
+    ok = reinterpret_cast<const v4i*>(a.counts_a)[r].z == a.n_f;
+  } else if (t < 32 * WM + 32 * WN) {
+    int64_t r = J0 + (t - 32 * WM);
+    r = r < a.n_b ? r : a.n_b - 1;
+    ok = reinterpret_cast<const v4i*>(a.counts_b)[r].z == a.n_f;
+  }
+  return __syncthreads_and(ok ? 1 : 0) != 0;
+}
+
 // ---------------------------------------------------------------------------
 // popcount path
 //
