@@ -157,6 +157,31 @@ def test_block_one_shot(path, n_a, n_b, n_f, missing):
 
 
 @pytest.mark.parametrize("path", PATHS)
+def test_block_complete_data_and_one_missing_entry(path):
+    """Complete A and B take the workgroup-cooperative one-plane form (MFMA)
+    in a one-shot block call; one missing entry in B sends only the
+    workgroups holding that row back to the general form."""
+    import torch
+    n_a, n_b, n_f = 200, 150, 3001
+    say("block complete", path)
+    va = synth.beta_hw(n_a, n_f, seed=61, missing=0.0)
+    vb = synth.beta_hw(n_b, n_f, seed=62, missing=0.0)
+    codes = oracle.brute.unpack_codes(vb, n_f)
+    codes[77, 1234] = 2
+    vb2 = synth.pack_codes(codes, pad_value=-1)
+    for b in (vb, vb2):
+        tables = torch.empty((n_a, n_b, 4), dtype=torch.int32, device="cuda")
+        ca = torch.empty((n_a, 4), dtype=torch.int32, device="cuda")
+        cb = torch.empty((n_b, 4), dtype=torch.int32, device="cuda")
+        cc = torch.empty((n_a, n_b, 4), dtype=torch.float64, device="cuda")
+        ccc.ccc_2way_block(dev(va), dev(b), n_f, tables, ca, cb, cc, path=path)
+        sync()
+        ot, oc = oracle.block(va, b, n_f)
+        assert_tables_equal(host(tables), ot)
+        assert_ccc_close(host(cc), oc)
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_block_chunked_equals_one_shot(path):
     import torch
     # 5 chunks of 1024 fields plus a ragged last chunk of 333, garbage padding

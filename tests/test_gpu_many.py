@@ -20,10 +20,10 @@ def sync():
     torch.cuda.synchronize()
 
 
-def make_batch(sizes, seed):
+def make_batch(sizes, seed, missing=0.02):
     hosts, probs = [], []
     for k, (n_v, n_f) in enumerate(sizes):
-        v = synth.beta_hw(n_v, n_f, seed=seed + k, missing=0.02)
+        v = synth.beta_hw(n_v, n_f, seed=seed + k, missing=missing)
         hosts.append(v)
         probs.append(dict(v=dev(v), n_f=n_f))
     return hosts, probs
@@ -53,6 +53,20 @@ def test_many_matches_oracle(variant, path):
         assert_tables_equal(host(t), ot)
         assert_ccc_close(host(c), oc)
         assert np.array_equal(host(cnt)[:, :3], oracle.counts1(v, n_f))
+
+
+@pytest.mark.parametrize("path", ["mfma", "popcount"])
+def test_many_complete_data_problems(variant, path):
+    """A batch with no missing entries: the persistent kernels take the
+    per-wave (MFMA) or per-workgroup (popcount) complete-data form."""
+    say("many complete", variant, path)
+    hosts, probs = make_batch(SIZES, seed=700, missing=0.0)
+    outs = ccc.ccc_2way_many(probs, path=path)
+    sync()
+    for (n_v, n_f), v, (t, c, _) in zip(SIZES, hosts, outs):
+        ot, oc = oracle.two_way(v, n_f)
+        assert_tables_equal(host(t), ot)
+        assert_ccc_close(host(c), oc)
 
 
 def test_many_graph_replays_with_eager_work_between(variant):
