@@ -247,6 +247,15 @@ def bench_3way(args, lib, missing, workload):
                              value=comps / (sms / 1e3),
                              note="ccc_3way_select: only triples with a CCC value >= threshold "
                                   "are written (includes a count read-back)")
+    if args.pop_steps > 0:
+        log(f"timing popcount 3-way: 1 warmup + {args.pop_steps} steps")
+
+        def pop_step():
+            ccc.ccc_3way(dv, n_f, tables, cc, counts, path="popcount")
+
+        pms, pkms, _ = timed(pop_step, args.pop_steps, 1, lib, "pop3")
+        out["popcount"] = dict(value=comps / (pms / 1e3), ms_per_step=pms, kernel_ms=pkms)
+        out["mfma_over_popcount"] = pms / ms
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_3way(v, n_f, 1)
     return out
@@ -374,7 +383,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--pop-steps", type=int, default=2, help="popcount-path steps (c2)")
+    ap.add_argument("--pop-steps", type=int, default=2,
+                    help="popcount-path steps (c2, c2c, c3, c3c)")
     ap.add_argument("--config", default="c2",
                     choices=["c1", "c2", "c2c", "c2m", "c3", "c3c", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

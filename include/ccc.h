@@ -114,7 +114,13 @@ int ccc_2way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* ta
  *   tables  int32 [C(n_v,3)][8] or NULL;  ccc double [C(n_v,3)][8] or NULL
  *   (at least one non-NULL);  counts as for ccc_2way.
  * n_v < 3 writes no tables.  CCC_ERR_RANGE if 8*n_f > INT32_MAX.
- * The path option selects the MFMA or popcount kernel.
+ * The path option selects the MFMA or popcount kernel.  Workspace: 8 bytes
+ * per pair of 64-row tiles (work-unit offsets), 16 bytes per vector when
+ * counts is NULL, and on the MFMA path the rho(1) Gram matrix that
+ * complete-data units read: 4 bytes per entry over the rows from the first
+ * staged row (i_begin of ccc_3way_rows, else 0) rounded down to 64, so n_v^2
+ * * 4 bytes for a whole call; beyond 32768 such rows it is not kept and every
+ * unit takes the general form.
  */
 int ccc_3way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
              double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream);
