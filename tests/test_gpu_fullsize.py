@@ -251,3 +251,39 @@ def test_c2_shape_complete_data_full_size():
     w, u = synth.weights(n_v, seed=9, tag=0), synth.weights(n_v, seed=9, tag=1)
     assert np.array_equal(oracle.fp2_from_tables(t.cpu().numpy(), n_v, w, u),
                           oracle.fp2_from_input(v, n_f, w, u))
+
+
+@pytest.mark.parametrize("missing", [0.0, 1e-6])
+def test_huge_field_count_exact_in_int32(missing):
+    """n_f = 2^27 + 3 fields (a ragged tail) for a handful of vectors: 2-way
+    entries reach 4 n_f ~ 2^29 and 3-way entries 8 n_f ~ 2^30, near the int32
+    limits the API enforces; the complete-data forms rebuild entries through
+    sums that wrap modulo 2^32 on the way.  Both paths, every table and CCC
+    value against the oracle."""
+    n_v, n_f = 5, (1 << 27) + 3
+    say("huge n_f", missing)
+    v = synth.beta_hw(n_v, n_f, seed=21, missing=missing)
+    dv = dev(v)
+    ot2, oc2 = oracle.two_way(v, n_f)
+    ot3, oc3 = oracle.three_way(v, n_f)
+    for path in ("mfma", "popcount"):
+        say("huge n_f", missing, path)
+        t, c, _ = ccc.ccc_2way(dv, n_f, path=path)
+        t3, c3, _ = ccc.ccc_3way(dv, n_f, path=path)
+        sync()
+        assert_tables_equal(t.cpu().numpy(), ot2)
+        assert_ccc_close(c.cpu().numpy(), oc2)
+        assert_tables_equal(t3.cpu().numpy(), ot3)
+        assert_ccc_close(c3.cpu().numpy(), oc3)
+    assert int(ot3.max()) > (1 << 29)  # the wide entries were exercised
+
+
+def test_huge_field_count_multi_allelic():
+    n_v, n_f, s = 4, (1 << 26) + 5, 4
+    say("huge n_f multi")
+    v = synth.multi_hw(n_v, n_f, s, seed=22, missing=0.0)
+    t, c, _ = ccc.ccc_2way_multi(dev(v), n_f, s)
+    sync()
+    ot, oc = oracle.multi_two_way(v, n_f, s)
+    assert_tables_equal(t.cpu().numpy(), ot)
+    assert_ccc_close(c.cpu().numpy(), oc)
