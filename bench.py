@@ -96,34 +96,46 @@ def timed(fn, steps, warmup, lib, kernel):
     return total / steps, (kms / kn if kn else None), kn
 
 
-def cpu_baseline_2way(v, n_f, rows):
+def oracle_sample(call, units, n_rows, chunk, seconds):
+    """Runs call(r0, r1) over consecutive row chunks from row 0 until `seconds`
+    of CPU time have passed (or the rows run out); returns (rows, units, s)."""
+    rows, done, dt = 0, 0, 0.0
+    while rows < n_rows and dt < seconds:
+        r1 = min(n_rows, rows + chunk)
+        t = time.perf_counter()
+        call(rows, r1)
+        dt += time.perf_counter() - t
+        done += sum(units(i) for i in range(rows, r1))
+        rows = r1
+    return rows, done, dt
+
+
+def cpu_baseline_2way(v, n_f, seconds):
     """The oracle on rows [0, rows) x all later vectors (plain loops, OpenMP)."""
     import oracle
     n_v = v.shape[0]
-    t = time.perf_counter()
-    oracle.two_way(v, n_f, 0, rows, with_ccc=True)
-    dt = time.perf_counter() - t
-    pairs = sum(n_v - 1 - i for i in range(rows))
+    rows, pairs, dt = oracle_sample(
+        lambda r0, r1: oracle.two_way(v, n_f, r0, r1, with_ccc=True),
+        lambda i: n_v - 1 - i, n_v, 8, seconds)
     return dict(value=pairs * n_f / dt, unit="comparisons/s", cores=oracle.num_threads(),
                 kind="oracle",
                 sample=f"rows i in [0,{rows}) x all j>i of the same input ({pairs} pairs x "
                        f"{n_f} fields, {dt:.1f} s)")
 
 
-def cpu_baseline_3way(v, n_f, rows):
+def cpu_baseline_3way(v, n_f, seconds):
     import oracle
     n_v = v.shape[0]
-    t = time.perf_counter()
-    oracle.three_way(v, n_f, 0, rows, with_ccc=True)
-    dt = time.perf_counter() - t
-    tri = sum((n_v - 1 - i) * (n_v - 2 - i) // 2 for i in range(rows))
+    rows, tri, dt = oracle_sample(
+        lambda r0, r1: oracle.three_way(v, n_f, r0, r1, with_ccc=True),
+        lambda i: (n_v - 1 - i) * (n_v - 2 - i) // 2, n_v, 1, seconds)
     return dict(value=tri * n_f / dt, unit="comparisons/s", cores=oracle.num_threads(),
                 kind="oracle",
                 sample=f"triples with i in [0,{rows}) of the same input ({tri} triples x "
                        f"{n_f} fields, {dt:.1f} s)")
 
 
-def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
+def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_seconds):
     import torch
     import paper_1705_08213_amd as ccc
     import synth
@@ -188,8 +200,8 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_rows):
         out["roofline"] = dict(bound="alu", achieved=None, peak=None, unit=None, frac=None,
                                traffic=None, kernel="pop2_kernel", kernel_ms=kms)
     if not args.no_cpu:
-        log(f"timing the CPU oracle on {cpu_rows} rows")
-        out["cpu_baseline"] = cpu_baseline_2way(v, n_f, cpu_rows)
+        log(f"timing the CPU oracle for about {cpu_seconds:g} s")
+        out["cpu_baseline"] = cpu_baseline_2way(v, n_f, cpu_seconds)
     return out
 
 
@@ -257,7 +269,7 @@ def bench_3way(args, lib, missing, workload):
         out["popcount"] = dict(value=comps / (pms / 1e3), ms_per_step=pms, kernel_ms=pkms)
         out["mfma_over_popcount"] = pms / ms
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_3way(v, n_f, 1)
+        out["cpu_baseline"] = cpu_baseline_3way(v, n_f, args.cpu_seconds)
     return out
 
 
@@ -299,11 +311,8 @@ def bench_multi(args, lib):
                              int8_ops_per_comparison=int(2 * s * s)))
     if not args.no_cpu:
         import oracle
-        rows = args.cpu_rows
-        t0 = time.perf_counter()
-        oracle.multi_two_way(v, n_f, s, 0, rows)
-        dt = time.perf_counter() - t0
-        pairs = sum(n_v - 1 - i for i in range(rows))
+        rows, pairs, dt = oracle_sample(lambda r0, r1: oracle.multi_two_way(v, n_f, s, r0, r1),
+                                        lambda i: n_v - 1 - i, n_v, 8, args.cpu_seconds)
         out["cpu_baseline"] = dict(value=pairs * n_f / dt, unit="comparisons/s",
                                    cores=oracle.num_threads(), kind="oracle",
                                    sample=f"rows i in [0,{rows}) x all j>i of the same input "
@@ -388,7 +397,8 @@ def main():
     ap.add_argument("--config", default="c2",
                     choices=["c1", "c2", "c2c", "c2m", "c3", "c3c", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU time the oracle baseline runs for (whole row chunks)")
     ap.add_argument("--select-threshold", type=float, default=None,
                     help="also time the threshold-filtered entry point (c2, c3); e.g. 0.13 "
                          "for 2-way, 0.05 for 3-way (independent vectors stay below 0.141 and "
@@ -419,14 +429,15 @@ def main():
     if args.config == "c2":
         out = bench_2way(args, lib, 32768, 65536, 0.01, "beta_hw", "mfma",
                          "2-way CCC large: n_v=32768 x n_f=65536, Beta(0.5,0.5)/Hardy-Weinberg, "
-                         "1% missing", args.cpu_rows)
+                         "1% missing", args.cpu_seconds)
     elif args.config == "c2c":
         out = bench_2way(args, lib, 32768, 65536, 0.0, "beta_hw", "mfma",
                          "2-way CCC, complete data: n_v=32768 x n_f=65536, "
-                         "Beta(0.5,0.5)/Hardy-Weinberg, no missing", args.cpu_rows)
+                         "Beta(0.5,0.5)/Hardy-Weinberg, no missing", args.cpu_seconds)
     elif args.config == "c1":
         out = bench_2way(args, lib, 512, 1000, 0.0, "uniform", "popcount",
-                         "2-way CCC: n_v=512 x n_f=1000, uniform genotypes, no missing", 512)
+                         "2-way CCC: n_v=512 x n_f=1000, uniform genotypes, no missing",
+                         args.cpu_seconds)
     elif args.config == "c3":
         out = bench_3way(args, lib, 0.005, "3-way CCC: n_v=2048 x n_f=16384, "
                                            "Beta(0.5,0.5)/Hardy-Weinberg, 0.5% missing")
