@@ -30,6 +30,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
+FP4_PEAK_TFLOPS = 10100.0    # MI355X dense fp4 (e2m1) MFMA, 10.1 PFLOP/s
+
+
+def mfma2_format(n_f):
+    """(operand format, dense peak in T(FL)OP/s, dtype tag) of the 2-way MFMA
+    kernel over n_f fields, as the library reports it."""
+    import paper_1705_08213_amd as ccc
+    fmt = ccc.two_way_operands(n_f)
+    return (fmt, FP4_PEAK_TFLOPS, "fp4") if fmt == "fp4" else (fmt, INT8_PEAK_TOPS, "i8")
 HBM_PEAK_GBS = 8000.0
 
 
@@ -159,11 +168,13 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_seconds):
     out = dict(metric="CCC comparisons/sec (pairs*n_f), bit-exact tables", value=rate,
                unit="comparisons/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="i8" if path == "mfma" else "u32", data="synthetic",
+               dtype=mfma2_format(n_f)[2] if path == "mfma" else "u32", data="synthetic",
                config=dict(workload=workload, n_v=n_v, n_f=n_f, missing=missing, path=path))
     if path == "mfma":
-        # 4 int8 MACs per comparison; with no missing entry anywhere every tile
-        # takes the one-plane complete-data form (1 MAC per comparison)
+        # 4 MACs per comparison (four operand-plane products); with no missing
+        # entry anywhere every tile takes the one-plane complete-data form (1 MAC)
+        fmt, peak, _ = mfma2_format(n_f)
+        out["config"]["operands"] = fmt
         ops = (2.0 if missing == 0.0 else 8.0) * comps
         ach = ops / (kms / 1e3) / 1e12
         traffic = None
@@ -171,12 +182,12 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_seconds):
             traffic = committed_traffic(
                 MFMA2_SOURCES, "profiles/mfma2_2way_n32768_f65536_traffic.md" if missing > 0.0
                 else "profiles/mfma2_2way_complete_n32768_f65536.md")
-        out["roofline"] = dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                               frac=ach / INT8_PEAK_TOPS, traffic=traffic,
+        out["roofline"] = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                               frac=ach / peak, traffic=traffic,
                                traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                                algorithmic_bytes=n_v * ((n_f + 3) // 4) + 48 * P + 32 * n_v,
-                               kernel="mfma2_kernel", kernel_ms=kms,
-                               int8_ops_per_comparison=2 if missing == 0.0 else 8)
+                               kernel="mfma2_kernel", kernel_ms=kms, operands=fmt,
+                               ops_per_comparison=2 if missing == 0.0 else 8)
         if args.select_threshold is not None:
             thr = args.select_threshold
             log(f"timing threshold selection at {thr}")
@@ -343,15 +354,16 @@ def bench_block(args, lib):
     comps = n * n * n_f
     per_launch = 8.0 * n * n * chunk
     ach = per_launch / (kms / 1e3) / 1e12
+    fmt, peak, dt = mfma2_format(chunk)
     return dict(metric="CCC comparisons/sec (n_a*n_b*n_f), bit-exact tables",
                 value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
-                vs_baseline=None, dtype="i8", data="synthetic",
+                vs_baseline=None, dtype=dt, data="synthetic",
                 config=dict(workload="2-way block 16384 x 16384, n_f=131072 in 8 chunks of "
-                                     "16384, Beta/HW, 2% missing", path="mfma"),
-                roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                              frac=ach / INT8_PEAK_TOPS, traffic=None, kernel="mfma2_kernel",
-                              kernel_ms=kms))
+                                     "16384, Beta/HW, 2% missing", path="mfma", operands=fmt),
+                roofline=dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                              frac=ach / peak, traffic=None, kernel="mfma2_kernel",
+                              kernel_ms=kms, operands=fmt))
 
 
 def bench_many(args, lib):
@@ -374,17 +386,18 @@ def bench_many(args, lib):
         ccc.ccc_2way_many(probs)
 
     ms, kms, kn = timed(step, args.steps, args.warmup, lib, "mfma2")
+    fmt, peak, dt = mfma2_format(int(nf.max()))
     return dict(metric="CCC comparisons/sec (sum pairs*n_f), bit-exact tables",
                 value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
-                vs_baseline=None, dtype="i8", data="synthetic",
+                vs_baseline=None, dtype=dt, data="synthetic",
                 config=dict(workload="64 batched 2-way problems, n_v log-uniform [256,8192], "
                                      "n_f uniform [1000,50000], Beta/HW, 1% missing",
-                            path="mfma"),
+                            path="mfma", operands=fmt),
                 roofline=dict(bound="mfma", achieved=8.0 * comps / (ms / 1e3) / 1e12,
-                              peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                              frac=8.0 * comps / (ms / 1e3) / 1e12 / INT8_PEAK_TOPS,
-                              traffic=None, kernel="whole step"))
+                              peak=peak, unit="TFLOP/s",
+                              frac=8.0 * comps / (ms / 1e3) / 1e12 / peak,
+                              traffic=None, kernel="whole step", operands=fmt))
 
 
 def main():

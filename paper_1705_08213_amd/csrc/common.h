@@ -15,6 +15,8 @@ namespace ccc {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 // 16 fields of the missing code (0b10 each).
 constexpr unsigned kAllMissing = 0xAAAAAAAAu;

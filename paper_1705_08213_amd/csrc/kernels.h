@@ -40,6 +40,10 @@ struct Pair2Args {
   Select sel;                 // threshold selection (sel.count != null) instead of dense output
 };
 
+// Largest n_f for which the 2-way MFMA kernels take fp4 operands (their fp32
+// sums of quarter-multiples, at most n_f, stay exact); int8 beyond.
+constexpr int64_t kF4MaxFields = int64_t(1) << 22;
+
 // Row tile of the 3-way work units (both 3-way kernels use it).
 constexpr int64_t kUnitTile = 64;
 

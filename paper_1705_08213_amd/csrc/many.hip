@@ -109,32 +109,36 @@ __device__ __forceinline__ int next_item(unsigned* counter, int* slot) {
   return it;
 }
 
-template <int WM, int WN>
-__device__ __forceinline__ void mfma_item(const Pair2Args& a, int64_t tiles_side, int tile) {
+template <int WM, int WN, bool F4>
+__device__ __forceinline__ void mfma_item(const Pair2Args& a, int64_t tiles_side, int tile,
+                                          u4 (*stage)[WM + WN][64]) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   const int wave = threadIdx.x >> 6;
   int64_t sq_i, sq_j;
   tri_tile(tile >> 1, tiles_side, sq_i, sq_j);
   const int64_t I = sq_i, J = 2 * sq_j + (tile & 1);
-  tile2::mfma2_wave_tile<WM, WN>(a, I * BM + (wave & 1) * 16 * WM, J * BN + (wave >> 1) * 16 * WN);
+  tile2::mfma2_wave_tile<WM, WN, F4>(a, I * BM + (wave & 1) * 16 * WM,
+                                     J * BN + (wave >> 1) * 16 * WN, stage + 2 * wave);
 }
 
 // One persistent launch per tile variant present in the batch (each variant's
 // items form their own list and counter), so every kernel keeps the register
-// budget of its own tile shape.
-template <int WM, int WN>
+// budget of its own tile shape.  F4: fp4 operands (every problem of the batch
+// has n_f <= kF4MaxFields), else int8.
+template <int WM, int WN, bool F4>
 __global__ __launch_bounds__(256, 2) void many_mfma_kernel(const ProbDesc* __restrict__ d,
                                                            const WorkItem* __restrict__ items,
                                                            int n_items,
                                                            unsigned* __restrict__ counter,
                                                            double gamma) {
   __shared__ int slot;
+  __shared__ u4 stage[4 * 2][WM + WN][64];  // two fp4 stage buffers per wave
   for (;;) {
     const int it = next_item(counter, &slot);
     if (it >= n_items) break;
     const WorkItem w = items[it];
     const ProbDesc p = d[w.prob];
-    mfma_item<WM, WN>(pair_args(p, gamma), p.tiles_side, w.tile);
+    mfma_item<WM, WN, F4>(pair_args(p, gamma), p.tiles_side, w.tile, stage);
   }
 }
 
@@ -227,6 +231,7 @@ struct Entry {
   int item_begin[kVariants] = {0, 0}, n_items[kVariants] = {0, 0};
   int64_t total_rows = 0;
   int path = 0;
+  bool f4 = true;                 // fp4 operands (all n_f <= kF4MaxFields)
   double gamma = 0;
   int grid[kVariants] = {0, 0};
   hipStream_t fork = nullptr;     // second capture stream for a concurrent variant
@@ -275,12 +280,18 @@ hipError_t launch_variant(const Entry& e, int v, hipStream_t stream) {
   if (e.path == CCC_PATH_POPCOUNT)
     hipLaunchKernelGGL(many_pop_kernel, dim3(e.grid[v]), dim3(256), 0, stream, e.d, items,
                        e.n_items[v], e.counters + v, e.gamma);
+  else if (v == 0 && e.f4)
+    hipLaunchKernelGGL((many_mfma_kernel<4, 2, true>), dim3(e.grid[v]), dim3(256), 0, stream, e.d,
+                       items, e.n_items[v], e.counters + v, e.gamma);
   else if (v == 0)
-    hipLaunchKernelGGL((many_mfma_kernel<4, 2>), dim3(e.grid[v]), dim3(256), 0, stream, e.d, items,
-                       e.n_items[v], e.counters + v, e.gamma);
+    hipLaunchKernelGGL((many_mfma_kernel<4, 2, false>), dim3(e.grid[v]), dim3(256), 0, stream,
+                       e.d, items, e.n_items[v], e.counters + v, e.gamma);
+  else if (e.f4)
+    hipLaunchKernelGGL((many_mfma_kernel<2, 1, true>), dim3(e.grid[v]), dim3(256), 0, stream, e.d,
+                       items, e.n_items[v], e.counters + v, e.gamma);
   else
-    hipLaunchKernelGGL((many_mfma_kernel<2, 1>), dim3(e.grid[v]), dim3(256), 0, stream, e.d, items,
-                       e.n_items[v], e.counters + v, e.gamma);
+    hipLaunchKernelGGL((many_mfma_kernel<2, 1, false>), dim3(e.grid[v]), dim3(256), 0, stream,
+                       e.d, items, e.n_items[v], e.counters + v, e.gamma);
   return hipGetLastError();
 }
 
@@ -323,6 +334,7 @@ int build_entry(const ccc_problem* probs, int n, const ccc_opts& o, Entry* e) {
     x.ccc = q.ccc;
     x.counts = q.counts;
     x.row_begin = rows;
+    if (q.n_f > kF4MaxFields) e->f4 = false;
     x.variant = o.path == CCC_PATH_POPCOUNT ? 0 : pick_variant(q.n_v, q.n_f, CCC_PATH_MFMA);
     const int side = o.path == CCC_PATH_POPCOUNT ? kPopTile : kSquare[x.variant];
     const int64_t T = (q.n_v + side - 1) / side;

@@ -7,7 +7,7 @@ namespace ccc {
 
 namespace {
 
-template <int WM, int WN>
+template <int WM, int WN, bool F4>
 __global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tiles_side,
                                                        int64_t tiles_n) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
@@ -25,12 +25,17 @@ __global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tile
     I = b / tiles_n;
     J = b % tiles_n;
   }
+  // 64 KB: the complete-data form's partial tiles, or else each wave's two
+  // fp4 stage buffers of WM + WN rows
   __shared__ v4i part[4][16][64];
+  static_assert(sizeof(part) >= 4 * 2 * (WM + WN) * 64 * sizeof(u4), "stage buffers fit");
   if (tile2::workgroup_complete<WM, WN>(a, I * BM, J * BN)) {
-    tile2::mfma2_coop_complete<WM, WN>(a, I * BM, J * BN, part);
+    tile2::mfma2_coop_complete<WM, WN, F4>(a, I * BM, J * BN, part);
     return;
   }
-  tile2::mfma2_wave_tile<WM, WN>(a, I * BM + (wave & 1) * 16 * WM, J * BN + (wave >> 1) * 16 * WN);
+  u4(*stage)[WM + WN][64] = reinterpret_cast<u4(*)[WM + WN][64]>(&part[0][0][0]) + 2 * wave;
+  tile2::mfma2_wave_tile<WM, WN, F4>(a, I * BM + (wave & 1) * 16 * WM,
+                                     J * BN + (wave >> 1) * 16 * WN, stage);
 }
 
 template <int WM, int WN>
@@ -47,8 +52,12 @@ hipError_t launch_shape(const Pair2Args& a, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   timing_begin("mfma2", stream);
-  hipLaunchKernelGGL((mfma2_kernel<WM, WN>), dim3((unsigned)ntiles), dim3(256), 0, stream, b, tm,
-                     tn);
+  if (a.n_f <= kF4MaxFields)
+    hipLaunchKernelGGL((mfma2_kernel<WM, WN, true>), dim3((unsigned)ntiles), dim3(256), 0, stream,
+                       b, tm, tn);
+  else
+    hipLaunchKernelGGL((mfma2_kernel<WM, WN, false>), dim3((unsigned)ntiles), dim3(256), 0,
+                       stream, b, tm, tn);
   timing_end(stream);
   return hipGetLastError();
 }

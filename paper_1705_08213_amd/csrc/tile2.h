@@ -3,6 +3,8 @@
 //
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -135,6 +137,176 @@ __device__ __forceinline__ void mma_superstep_rho1(const u4 (&pa)[WM], const u4 
   }
 }
 
+// ---------------------------------------------------------------------------
+// fp4 operands (e2m1, the 16x16x128 scaled MFMA at twice the int8 rate)
+//
+// A 2-bit value x in the low two bits of a nibble is the e2m1 number x / 2
+// (0001 is the subnormal 1/2, 0010 is 1).  The planes used are rho(1) and
+// the presence P (code != 10); from the code's bits lo, hi:
+//   rho(1) = lo + (lo & hi)  (00 -> 0, 01 -> 1, 11 -> 2, 10 -> 0),
+//   P      = lo | !hi,
+// five operations per 16 fields, computed on the packed word, whose 2-bit
+// fields then go to nibbles (even fields, then odd ones: A and B share the
+// order).  Products are multiples of 1/4 and a sum over n_f fields is at most
+// n_f, so fp32 accumulation is exact while n_f <= 2^22 (kF4MaxFields); the
+// four sums S = sum rho_i rho_j, T = sum rho_i P_j, U = sum P_i rho_j,
+// V = sum P_i P_j (each 4x the accumulated value) give the table:
+//   C11 = S,  C10 = 2T - S,  C01 = 2U - S,  C00 = 4V - 2T - 2U + S
+// (rho(0) = 2P - rho(1)).  Fields past n_f carry the missing code, which is
+// zero in both planes.
+// ---------------------------------------------------------------------------
+
+constexpr unsigned kEven2 = 0x55555555u;  // bit 0 of every 2-bit field
+constexpr unsigned kNib2 = 0x33333333u;   // low two bits of every nibble
+
+// The rho(1) and P planes of 16 fields as one fp4 operand half each:
+// r = (rho(1) of even fields, of odd fields), p likewise (see nibbles32).
+__device__ __forceinline__ void planes16_f4(unsigned w, unsigned (&r)[2], unsigned (&p)[2]) {
+  const unsigned s = w >> 1, lo = w & kEven2;
+  const unsigned r1 = lo + (lo & s);
+  r[0] = r1 & kNib2;
+  r[1] = (r1 >> 2) & kNib2;
+  const unsigned pres = w | ~s;  // bit 0 of each field: lo | !hi
+  p[0] = pres & 0x11111111u;
+  p[1] = (pres & 0x44444444u) >> 2;
+}
+
+// rho(1) of 16 fields; `complete` words hold no missing code, where
+// rho(1) = code - hi.
+template <bool complete>
+__device__ __forceinline__ unsigned rho1_16_f4(unsigned w) {
+  if (complete) return w - ((w >> 1) & kEven2);
+  const unsigned lo = w & kEven2;
+  return lo + (lo & (w >> 1));
+}
+
+// Two words of 2-bit values -> one fp4 operand of 32 nibbles (4 registers).
+__device__ __forceinline__ v8i nibbles32(unsigned x0, unsigned x1) {
+  return v8i{(int)(x0 & kNib2), (int)((x0 >> 2) & kNib2), (int)(x1 & kNib2),
+             (int)((x1 >> 2) & kNib2), 0, 0, 0, 0};
+}
+
+__device__ __forceinline__ v8i operand_f4(const unsigned (&x0)[2], const unsigned (&x1)[2]) {
+  return v8i{(int)x0[0], (int)x0[1], (int)x1[0], (int)x1[1], 0, 0, 0, 0};
+}
+
+__device__ __forceinline__ v4f mfma_f4(const v8i& a, const v8i& b, v4f c) {
+  // formats 4 = e2m1 for A and B; E8M0 scales 127 = 2^0
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+}
+
+__device__ __forceinline__ int f4_count(float x) { return (int)(4.0f * x); }
+
+// Table (entry 2a+b) from the four fp4 sums.
+__device__ __forceinline__ v4i table_f4(float s, float t, float u, float v) {
+  const int S = f4_count(s), T = f4_count(t), U = f4_count(u), V = f4_count(v);
+  return v4i{4 * V - 2 * T - 2 * U + S, 2 * U - S, 2 * T - S, S};
+}
+
+// One 256-field super-step (16 bytes per lane and row) of the four sums:
+// two MFMA steps of 128 fields.
+template <int WM, int WN>
+__device__ __forceinline__ void mma_superstep_f4(const u4 (&xa)[WM], const u4 (&xb)[WN],
+                                                 v4f (&acc)[WM][WN][4]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    v8i b0[WN], b1[WN];  // rho(1) and P planes
+#pragma unroll
+    for (int n = 0; n < WN; ++n) {
+      unsigned r0[2], p0[2], r1[2], p1[2];
+      planes16_f4(word_of(xb[n], 2 * h), r0, p0);
+      planes16_f4(word_of(xb[n], 2 * h + 1), r1, p1);
+      b0[n] = operand_f4(r0, r1);
+      b1[n] = operand_f4(p0, p1);
+    }
+#pragma unroll
+    for (int m = 0; m < WM; ++m) {
+      unsigned r0[2], p0[2], r1[2], p1[2];
+      planes16_f4(word_of(xa[m], 2 * h), r0, p0);
+      planes16_f4(word_of(xa[m], 2 * h + 1), r1, p1);
+      const v8i a0 = operand_f4(r0, r1), a1 = operand_f4(p0, p1);
+#pragma unroll
+      for (int n = 0; n < WN; ++n) {
+        acc[m][n][0] = mfma_f4(a0, b0[n], acc[m][n][0]);
+        acc[m][n][1] = mfma_f4(a0, b1[n], acc[m][n][1]);
+        acc[m][n][2] = mfma_f4(a1, b0[n], acc[m][n][2]);
+        acc[m][n][3] = mfma_f4(a1, b1[n], acc[m][n][3]);
+      }
+    }
+  }
+}
+
+// 16 bytes per lane of one row copied straight into LDS (lane l's bytes at
+// dst + 16 l), asynchronously: the wave's vector-memory counter covers it.
+__device__ __forceinline__ void stage_row(const uint8_t* src, u4* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+// The super-step loop of a wave tile for the fp4 form.  The next
+// super-step's rows travel from memory straight into this wave's LDS stage
+// (two buffers of WN + WM rows x 64 lanes x 16 bytes) while the current one
+// is unpacked and multiplied, so no registers hold them in flight; each step
+// starts by waiting for its buffer and reading it into registers.  Then one
+// masked tail step from plain loads.  Row pointers include the lane's 16g
+// byte offset.
+template <int WM, int WN, typename Step>
+__device__ __forceinline__ void wave_loop_f4(const uint8_t* const (&pa)[WM],
+                                             const uint8_t* const (&pb)[WN], int g, int64_t n_f,
+                                             u4 (*stage)[WM + WN][64], Step step) {
+  const int64_t nfull = n_f / 256;
+  const int64_t nbytes = (n_f + 3) / 4;
+  const int lane = threadIdx.x & 63;
+  auto issue = [&](int64_t s, int buf) {
+#pragma unroll
+    for (int n = 0; n < WN; ++n) stage_row(pb[n] + s * 64, &stage[buf][n][0]);
+#pragma unroll
+    for (int m = 0; m < WM; ++m) stage_row(pa[m] + s * 64, &stage[buf][WN + m][0]);
+  };
+  if (nfull > 0) issue(0, 0);
+  for (int64_t s = 0; s < nfull; ++s) {
+    const int buf = (int)(s & 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's rows are in LDS
+    u4 xa[WM], xb[WN];
+#pragma unroll
+    for (int n = 0; n < WN; ++n) xb[n] = stage[buf][n][lane];
+#pragma unroll
+    for (int m = 0; m < WM; ++m) xa[m] = stage[buf][WN + m][lane];
+    if (s + 1 < nfull) issue(s + 1, buf ^ 1);
+    step(xa, xb);
+  }
+  const int64_t kt = nfull * 64;
+  if (kt < nbytes) {
+    u4 xa[WM], xb[WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kt + 16 * g, n_f);
+#pragma unroll
+    for (int n = 0; n < WN; ++n) xb[n] = load_fields64(pb[n] - 16 * g, kt + 16 * g, n_f);
+    step(xa, xb);
+  }
+}
+
+// Complete-data super-step of S alone.
+template <int WM, int WN, bool complete>
+__device__ __forceinline__ void mma_superstep_rho1_f4(const u4 (&pa)[WM], const u4 (&pb)[WN],
+                                                      v4f (&acc)[WM][WN]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    v8i a1[WM], b1[WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+      a1[m] = nibbles32(rho1_16_f4<complete>(word_of(pa[m], 2 * h)),
+                        rho1_16_f4<complete>(word_of(pa[m], 2 * h + 1)));
+#pragma unroll
+    for (int n = 0; n < WN; ++n)
+      b1[n] = nibbles32(rho1_16_f4<complete>(word_of(pb[n], 2 * h)),
+                        rho1_16_f4<complete>(word_of(pb[n], 2 * h + 1)));
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+      for (int n = 0; n < WN; ++n) acc[m][n] = mfma_f4(a1[m], b1[n], acc[m][n]);
+  }
+}
+
 // Run the super-step loop of a wave tile: `step` consumes the 16-byte pieces
 // of every row (plain loads while all 256 fields are inside n_f, prefetched
 // one super-step ahead; then one masked tail step).
@@ -198,8 +370,10 @@ __device__ __forceinline__ void mma_superstep(const u4 (&pa)[WM], const u4 (&pb)
 // One wave's (16 WM) x (16 WN) tile of pairs with first row row0 and first
 // column col0 (see the design notes above).  Waves whose tile holds no pair
 // to compute return at once; no barrier is used, so callers may skip waves.
-template <int WM, int WN>
-__device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0, int64_t col0) {
+// `stage`: this wave's two LDS buffers of WM + WN rows (fp4 form only).
+template <int WM, int WN, bool F4>
+__device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0, int64_t col0,
+                                                u4 (*stage)[WM + WN][64]) {
   const int lane = threadIdx.x & 63;
   if (row0 >= a.n_a || col0 >= a.n_b) return;
   if (a.tri && row0 >= col0 + 16 * WN - 1) return;  // no pair i < j in this wave tile
@@ -237,13 +411,17 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     mine = mine && reinterpret_cast<const v4i*>(a.counts_b)[r].z == a.n_f;
   }
   if (__all(mine ? 1 : 0)) {
-    v4i acc1[WM][WN];
+    using Acc = std::conditional_t<F4, v4f, v4i>;
+    Acc acc1[WM][WN];
 #pragma unroll
     for (int m = 0; m < WM; ++m)
 #pragma unroll
-      for (int n = 0; n < WN; ++n) acc1[m][n] = v4i{0, 0, 0, 0};
+      for (int n = 0; n < WN; ++n) acc1[m][n] = Acc{0, 0, 0, 0};
     wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
-      mma_superstep_rho1<WM, WN>(ca, cb, acc1);
+      if constexpr (F4)
+        mma_superstep_rho1_f4<WM, WN, false>(ca, cb, acc1);
+      else
+        mma_superstep_rho1<WM, WN>(ca, cb, acc1);
     });
     const int nf4 = (int)(4 * a.n_f);
     double wj[WN][2];
@@ -265,7 +443,11 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
 #pragma unroll
         for (int n = 0; n < WN; ++n) {
           const int64_t j = col0 + 16 * n + rl;
-          const int c11 = acc1[m][n][e];
+          int c11;
+          if constexpr (F4)
+            c11 = f4_count(acc1[m][n][e]);
+          else
+            c11 = acc1[m][n][e];
           const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
           emit_pair(a, valid, i, j,
                     v4i{nf4 - 2 * n1i - 2 * n1j[n] + c11, 2 * n1j[n] - c11, 2 * n1i - c11, c11},
@@ -275,16 +457,23 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     return;
   }
 
-  v4i acc[WM][WN][4];
+  using Acc = std::conditional_t<F4, v4f, v4i>;
+  Acc acc[WM][WN][4];
 #pragma unroll
   for (int m = 0; m < WM; ++m)
 #pragma unroll
     for (int n = 0; n < WN; ++n)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[m][n][e] = v4i{0, 0, 0, 0};
-  wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
-    mma_superstep<WM, WN>(ca, cb, acc);
-  });
+      for (int e = 0; e < 4; ++e) acc[m][n][e] = Acc{0, 0, 0, 0};
+  if constexpr (F4) {
+    wave_loop_f4<WM, WN>(pa, pb, g, a.n_f, stage,
+                         [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
+                           mma_superstep_f4<WM, WN>(xa, xb, acc);
+                         });
+  } else
+    wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
+      mma_superstep<WM, WN>(ca, cb, acc);
+    });
 
   // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
 #pragma unroll
@@ -301,9 +490,12 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
       for (int e = 0; e < 4; ++e) {
         const int64_t i = row0 + 16 * m + 4 * g + e;
         const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
-        emit_pair(a, valid, i, j,
-                  v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]},
-                  wi[e], wj);
+        v4i t;
+        if constexpr (F4)
+          t = table_f4(acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]);
+        else
+          t = v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]};
+        emit_pair(a, valid, i, j, t, wi[e], wj);
       }
     }
   }
@@ -319,7 +511,7 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
 // through LDS (`part`, 4 x 16 x 64 x 16 bytes) in two halves of 16 blocks;
 // wave w keeps block rows 2w and 2w+1 and finishes their pairs.  Every thread
 // of the workgroup must call it (barriers).
-template <int WM, int WN>
+template <int WM, int WN, bool F4>
 __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t I0, int64_t J0,
                                                     v4i (*part)[16][64]) {
   constexpr int TM = 2 * WM, TN = 2 * WN;  // 16x16 blocks of the workgroup tile
@@ -338,24 +530,44 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
     const int64_t r = J0 + 16 * n + rl;
     pb[n] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
   }
-  v4i acc[TM][TN];
+  using Acc = std::conditional_t<F4, v4f, v4i>;
+  Acc acc[TM][TN];
 #pragma unroll
   for (int m = 0; m < TM; ++m)
 #pragma unroll
-    for (int n = 0; n < TN; ++n) acc[m][n] = v4i{0, 0, 0, 0};
+    for (int n = 0; n < TN; ++n) acc[m][n] = Acc{0, 0, 0, 0};
 
-  auto body = [&](const u4 (&xa)[TM], const u4 (&xb)[TN]) {
+  // `complete`: every field of the step is inside n_f (no padding code)
+  auto body = [&](const u4 (&xa)[TM], const u4 (&xb)[TN], auto complete) {
+    if constexpr (F4) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      v4i b1[TN];
-#pragma unroll
-      for (int n = 0; n < TN; ++n) b1[n] = unpack16_rho1(word_of(xb[n], s));
-#pragma unroll
-      for (int m = 0; m < TM; ++m) {
-        const v4i a1 = unpack16_rho1(word_of(xa[m], s));
+      for (int h = 0; h < 2; ++h) {
+        v8i b1[TN];
 #pragma unroll
         for (int n = 0; n < TN; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1[n], acc[m][n], 0, 0, 0);
+          b1[n] = nibbles32(rho1_16_f4<complete.value>(word_of(xb[n], 2 * h)),
+                            rho1_16_f4<complete.value>(word_of(xb[n], 2 * h + 1)));
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          const v8i a1 = nibbles32(rho1_16_f4<complete.value>(word_of(xa[m], 2 * h)),
+                                   rho1_16_f4<complete.value>(word_of(xa[m], 2 * h + 1)));
+#pragma unroll
+          for (int n = 0; n < TN; ++n) acc[m][n] = mfma_f4(a1, b1[n], acc[m][n]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        v4i b1[TN];
+#pragma unroll
+        for (int n = 0; n < TN; ++n) b1[n] = unpack16_rho1(word_of(xb[n], s));
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          const v4i a1 = unpack16_rho1(word_of(xa[m], s));
+#pragma unroll
+          for (int n = 0; n < TN; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1[n], acc[m][n], 0, 0, 0);
+        }
       }
     }
   };
@@ -370,7 +582,7 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
     for (int m = 0; m < TM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
 #pragma unroll
     for (int n = 0; n < TN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
-    body(xa, xb);
+    body(xa, xb, std::true_type{});
   }
   if (nfull >= s_begin && nfull < s_end) {
     const int64_t kb = nfull * 64 + 16 * g;
@@ -379,7 +591,7 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
     for (int m = 0; m < TM; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
 #pragma unroll
     for (int n = 0; n < TN; ++n) xb[n] = load_fields64(pb[n] - 16 * g, kb, a.n_f);
-    body(xa, xb);
+    body(xa, xb, std::false_type{});
   }
 
   // Sum the four partial tiles: half h holds block rows 4h..4h+3, owned by
@@ -390,7 +602,15 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < TN; ++n) part[wave][m * TN + n][lane] = acc[4 * h + m][n];
+      for (int n = 0; n < TN; ++n) {
+        if constexpr (F4) {
+          const v4f x = acc[4 * h + m][n];
+          part[wave][m * TN + n][lane] =
+              v4i{f4_count(x[0]), f4_count(x[1]), f4_count(x[2]), f4_count(x[3])};
+        } else {
+          part[wave][m * TN + n][lane] = acc[4 * h + m][n];
+        }
+      }
     __syncthreads();
     if ((wave >> 1) == h) {
 #pragma unroll
