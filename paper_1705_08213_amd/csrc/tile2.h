@@ -161,14 +161,16 @@ constexpr unsigned kNib2 = 0x33333333u;   // low two bits of every nibble
 
 // The rho(1) and P planes of 16 fields as one fp4 operand half each:
 // r = (rho(1) of even fields, of odd fields), p likewise (see nibbles32).
+// Ten operations: v_bitop3 truth tables 0x80 = a & b & c and
+// 0xA2 = c & (a | ~b) (with a = w, b = w >> 1: bit 0 of a field is lo, of
+// b is hi).
 __device__ __forceinline__ void planes16_f4(unsigned w, unsigned (&r)[2], unsigned (&p)[2]) {
-  const unsigned s = w >> 1, lo = w & kEven2;
-  const unsigned r1 = lo + (lo & s);
+  const unsigned s = w >> 1;
+  const unsigned r1 = (w & kEven2) + __builtin_amdgcn_bitop3_b32(w, s, kEven2, 0x80);
   r[0] = r1 & kNib2;
   r[1] = (r1 >> 2) & kNib2;
-  const unsigned pres = w | ~s;  // bit 0 of each field: lo | !hi
-  p[0] = pres & 0x11111111u;
-  p[1] = (pres & 0x44444444u) >> 2;
+  p[0] = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
+  p[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
 }
 
 // rho(1) of 16 fields; `complete` words hold no missing code, where
@@ -576,13 +578,40 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
   const int64_t steps = (a.n_f + 255) / 256, nfull = a.n_f / 256;
   const int64_t s_begin = steps * wave / 4, s_end = steps * (wave + 1) / 4;
   const int64_t e_full = s_end < nfull ? s_end : nfull;
-  for (int64_t st = s_begin; st < e_full; ++st) {
-    u4 xa[TM], xb[TN];
+  if constexpr (F4) {
+    // The rows travel straight into this wave's LDS stage (TN + TM rows x 64
+    // lanes x 16 bytes, inside `part`): each step waits for its rows, reads
+    // them into registers, and once those reads are back issues the next
+    // step's copy into the same buffer, which then lands during the MFMAs.
+    u4(*stage)[64] = reinterpret_cast<u4(*)[64]>(&part[0][0][0]) + wave * (TM + TN);
+    auto issue = [&](int64_t st) {
 #pragma unroll
-    for (int m = 0; m < TM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
+      for (int n = 0; n < TN; ++n) stage_row(pb[n] + st * 64, &stage[n][0]);
 #pragma unroll
-    for (int n = 0; n < TN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
-    body(xa, xb, std::true_type{});
+      for (int m = 0; m < TM; ++m) stage_row(pa[m] + st * 64, &stage[TN + m][0]);
+    };
+    if (s_begin < e_full) issue(s_begin);
+    for (int64_t st = s_begin; st < e_full; ++st) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's rows are in LDS
+      u4 xa[TM], xb[TN];
+#pragma unroll
+      for (int n = 0; n < TN; ++n) xb[n] = stage[n][lane];
+#pragma unroll
+      for (int m = 0; m < TM; ++m) xa[m] = stage[TN + m][lane];
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // read before it is overwritten
+      if (st + 1 < e_full) issue(st + 1);
+      body(xa, xb, std::true_type{});
+    }
+    __syncthreads();  // every wave's stage is done before `part` is reused below
+  } else {
+    for (int64_t st = s_begin; st < e_full; ++st) {
+      u4 xa[TM], xb[TN];
+#pragma unroll
+      for (int m = 0; m < TM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
+#pragma unroll
+      for (int n = 0; n < TN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
+      body(xa, xb, std::true_type{});
+    }
   }
   if (nfull >= s_begin && nfull < s_end) {
     const int64_t kb = nfull * 64 + 16 * g;
