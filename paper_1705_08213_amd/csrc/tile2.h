@@ -578,40 +578,13 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
   const int64_t steps = (a.n_f + 255) / 256, nfull = a.n_f / 256;
   const int64_t s_begin = steps * wave / 4, s_end = steps * (wave + 1) / 4;
   const int64_t e_full = s_end < nfull ? s_end : nfull;
-  if constexpr (F4) {
-    // The rows travel straight into this wave's LDS stage (TN + TM rows x 64
-    // lanes x 16 bytes, inside `part`): each step waits for its rows, reads
-    // them into registers, and once those reads are back issues the next
-    // step's copy into the same buffer, which then lands during the MFMAs.
-    u4(*stage)[64] = reinterpret_cast<u4(*)[64]>(&part[0][0][0]) + wave * (TM + TN);
-    auto issue = [&](int64_t st) {
+  for (int64_t st = s_begin; st < e_full; ++st) {
+    u4 xa[TM], xb[TN];
 #pragma unroll
-      for (int n = 0; n < TN; ++n) stage_row(pb[n] + st * 64, &stage[n][0]);
+    for (int m = 0; m < TM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
 #pragma unroll
-      for (int m = 0; m < TM; ++m) stage_row(pa[m] + st * 64, &stage[TN + m][0]);
-    };
-    if (s_begin < e_full) issue(s_begin);
-    for (int64_t st = s_begin; st < e_full; ++st) {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's rows are in LDS
-      u4 xa[TM], xb[TN];
-#pragma unroll
-      for (int n = 0; n < TN; ++n) xb[n] = stage[n][lane];
-#pragma unroll
-      for (int m = 0; m < TM; ++m) xa[m] = stage[TN + m][lane];
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // read before it is overwritten
-      if (st + 1 < e_full) issue(st + 1);
-      body(xa, xb, std::true_type{});
-    }
-    __syncthreads();  // every wave's stage is done before `part` is reused below
-  } else {
-    for (int64_t st = s_begin; st < e_full; ++st) {
-      u4 xa[TM], xb[TN];
-#pragma unroll
-      for (int m = 0; m < TM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
-#pragma unroll
-      for (int n = 0; n < TN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
-      body(xa, xb, std::true_type{});
-    }
+    for (int n = 0; n < TN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
+    body(xa, xb, std::true_type{});
   }
   if (nfull >= s_begin && nfull < s_end) {
     const int64_t kb = nfull * 64 + 16 * g;
