@@ -33,11 +33,11 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 FP4_PEAK_TFLOPS = 10100.0    # MI355X dense fp4 (e2m1) MFMA, 10.1 PFLOP/s
 
 
-def mfma2_format(n_f):
-    """(operand format, dense peak in T(FL)OP/s, dtype tag) of the 2-way MFMA
-    kernel over n_f fields, as the library reports it."""
+def mfma_format(n_f):
+    """(operand format, dense peak in T(FL)OP/s, dtype tag) of the 2-way and
+    3-way MFMA kernels over n_f fields, as the library reports it."""
     import paper_1705_08213_amd as ccc
-    fmt = ccc.two_way_operands(n_f)
+    fmt = ccc.mfma_operands(n_f)
     return (fmt, FP4_PEAK_TFLOPS, "fp4") if fmt == "fp4" else (fmt, INT8_PEAK_TOPS, "i8")
 HBM_PEAK_GBS = 8000.0
 
@@ -168,12 +168,12 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_seconds):
     out = dict(metric="CCC comparisons/sec (pairs*n_f), bit-exact tables", value=rate,
                unit="comparisons/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype=mfma2_format(n_f)[2] if path == "mfma" else "u32", data="synthetic",
+               dtype=mfma_format(n_f)[2] if path == "mfma" else "u32", data="synthetic",
                config=dict(workload=workload, n_v=n_v, n_f=n_f, missing=missing, path=path))
     if path == "mfma":
         # 4 MACs per comparison (four operand-plane products); with no missing
         # entry anywhere every tile takes the one-plane complete-data form (1 MAC)
-        fmt, peak, _ = mfma2_format(n_f)
+        fmt, peak, _ = mfma_format(n_f)
         out["config"]["operands"] = fmt
         ops = (2.0 if missing == 0.0 else 8.0) * comps
         ach = ops / (kms / 1e3) / 1e12
@@ -234,16 +234,17 @@ def bench_3way(args, lib, missing, workload):
 
     ms, kms, _ = timed(step, args.steps, args.warmup, lib, "mfma3")
     comps = T * n_f
-    # 8 int8 MACs per comparison; with no missing entry every unit takes the
+    # 8 MACs per comparison; with no missing entry every unit takes the
     # one-plane complete-data form (1 MAC per comparison)
+    fmt, peak, dt = mfma_format(n_f)
     ops_per = 2.0 if missing == 0.0 else 16.0
     ach = ops_per * comps / (kms / 1e3) / 1e12
     alg_bytes = n_v * ((n_f + 3) // 4) + 96 * T + 16 * n_v
-    roof = dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                frac=ach / INT8_PEAK_TOPS, traffic=None,
+    roof = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                frac=ach / peak, traffic=None,
                 traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                 algorithmic_bytes=alg_bytes, kernel="mfma3_kernel", kernel_ms=kms,
-                int8_ops_per_comparison=int(ops_per))
+                operands=fmt, ops_per_comparison=int(ops_per))
     roof["traffic"] = committed_traffic(
         MFMA3_SOURCES, "profiles/mfma3_3way_n2048_f16384.md" if missing > 0.0
         else "profiles/mfma3_3way_complete_n2048_f16384.md")
@@ -251,12 +252,13 @@ def bench_3way(args, lib, missing, workload):
     if hbm / HBM_PEAK_GBS > roof["frac"]:
         # the output stream, not the matrix cores, is the nearer ceiling
         roof.update(bound="hbm", achieved=hbm, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=hbm / HBM_PEAK_GBS, mfma_frac=ach / INT8_PEAK_TOPS)
+                    frac=hbm / HBM_PEAK_GBS, mfma_frac=ach / peak)
     out = dict(metric="CCC comparisons/sec (triples*n_f), bit-exact tables",
                value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="i8", data="synthetic",
-               config=dict(workload=workload, n_v=n_v, n_f=n_f, missing=missing, path="mfma"),
+               vs_baseline=None, dtype=dt, data="synthetic",
+               config=dict(workload=workload, n_v=n_v, n_f=n_f, missing=missing, path="mfma",
+                           operands=fmt),
                roofline=roof)
     if args.select_threshold is not None:
         thr = args.select_threshold
@@ -354,7 +356,7 @@ def bench_block(args, lib):
     comps = n * n * n_f
     per_launch = 8.0 * n * n * chunk
     ach = per_launch / (kms / 1e3) / 1e12
-    fmt, peak, dt = mfma2_format(chunk)
+    fmt, peak, dt = mfma_format(chunk)
     return dict(metric="CCC comparisons/sec (n_a*n_b*n_f), bit-exact tables",
                 value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
@@ -386,7 +388,7 @@ def bench_many(args, lib):
         ccc.ccc_2way_many(probs)
 
     ms, kms, kn = timed(step, args.steps, args.warmup, lib, "mfma2")
-    fmt, peak, dt = mfma2_format(int(nf.max()))
+    fmt, peak, dt = mfma_format(int(nf.max()))
     return dict(metric="CCC comparisons/sec (sum pairs*n_f), bit-exact tables",
                 value=comps / (ms / 1e3), unit="comparisons/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",

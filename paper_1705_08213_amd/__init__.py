@@ -82,8 +82,8 @@ def lib():
         L.ccc_status_string.argtypes = [cint]
         L.ccc_status_string.restype = ctypes.c_char_p
         L.ccc_version.restype = cint
-        L.ccc_2way_operands.argtypes = [i64]
-        L.ccc_2way_operands.restype = cint
+        L.ccc_mfma_operands.argtypes = [i64]
+        L.ccc_mfma_operands.restype = cint
         L.ccc_default_opts.restype = ccc_opts
         L.ccc_release_workspace.restype = None
         _lib = L
@@ -105,10 +105,10 @@ def version() -> int:
     return lib().ccc_version()
 
 
-def two_way_operands(n_f: int) -> str:
-    """Operand format of a 2-way MFMA call over n_f fields: "fp4" or "int8"."""
-    r = lib().ccc_2way_operands(n_f)
-    _raise(r if r < 0 else 0, "ccc_2way_operands")
+def mfma_operands(n_f: int) -> str:
+    """Operand format of a 2-way or 3-way MFMA call over n_f fields: "fp4" or "int8"."""
+    r = lib().ccc_mfma_operands(n_f)
+    _raise(r if r < 0 else 0, "ccc_mfma_operands")
     return {4: "fp4", 8: "int8"}[r]
 
 

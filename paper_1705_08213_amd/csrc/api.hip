@@ -101,7 +101,7 @@ ccc_opts ccc_default_opts(void) {
 
 int ccc_version(void) { return 100; }
 
-int ccc_2way_operands(int64_t n_f) {
+int ccc_mfma_operands(int64_t n_f) {
   if (n_f < 0) return CCC_ERR_ARG;
   return n_f <= ccc::kF4MaxFields ? CCC_OPERANDS_FP4 : CCC_OPERANDS_INT8;
 }

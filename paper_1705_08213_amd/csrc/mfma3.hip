@@ -31,6 +31,8 @@
 // (expand the product of (2 - x) and x factors).  One MFMA plane replaces
 // eight.  Such a unit is computed by all four waves on one 64 x 64 tile, each
 // over a quarter of the fields, and the partial sums are added through LDS.
+#include <type_traits>
+
 #include "tile2.h"
 #include "tile3.h"
 
@@ -63,10 +65,190 @@ __device__ __forceinline__ void codes4(unsigned w, unsigned (&c)[4]) {
   c[3] = (w >> 6) & kLow2;
 }
 
+// ---------------------------------------------------------------------------
+// fp4 form (n_f <= kF4MaxFields; operands as in the 2-way fp4 form: a 2-bit
+// value x in a nibble is the e2m1 number x / 2).  Planes rho(1) = R and P for
+// i and k; D = rho(1) - P (values -1, 0, 1) and P for j.  The k-side operands
+// are modulated by j field by field:
+//   D_j Z_k: Z_k's nibble where D_j != 0, with the e2m1 sign bit set where
+//            D_j = -1 (code 00): one v_bitop3, (z & m) ^ sign;
+//   P_j Z_k: Z_k's nibble where P_j = 1: one AND.
+// The eight sums S[x][y][z] = sum x_i y_j z_k (x, z in {R, P}, y in {D, P};
+// each is 4x its fp32 accumulator, a multiple of 1/4 of magnitude <= n_f,
+// exact) give the table through rho(1) = R, rho(0) = 2P - R on i and k and
+// rho_j(1) = D + P, rho_j(0) = P - D.
+
+// j's masks for the two operand registers (even, odd fields) of one packed
+// word: y = both value bits where D != 0, sg = the sign bit where D = -1,
+// p = both value bits where P = 1.  v_bitop3 tables on (a = w, b = w >> 1,
+// c = field mask): 0x82 = c & ~(a ^ b), 0x02 = c & ~a & ~b, 0xA2 = c & (a | ~b).
+__device__ __forceinline__ void j_masks_f4(unsigned w, unsigned* y, unsigned* sg, unsigned* p) {
+  const unsigned s = w >> 1;
+  unsigned t = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0x82);
+  y[0] = t | (t << 1);
+  t = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0x82) >> 2;
+  y[1] = t | (t << 1);
+  sg[0] = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0x02) << 3;
+  sg[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0x02) << 1;
+  if (p) {
+    t = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
+    p[0] = t | (t << 1);
+    t = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
+    p[1] = t | (t << 1);
+  }
+}
+
+// (z & m) ^ sg: z modulated by D_j.
+__device__ __forceinline__ unsigned mod_d(unsigned z, unsigned m, unsigned sg) {
+  return __builtin_amdgcn_bitop3_b32(z, m, sg, 0x6A);
+}
+
+// Table entry 4a + 2b + c from the eight sums (index 4x + 2y + z).
+__device__ __forceinline__ void table3_f4(const int (&S)[8], int (&t)[8]) {
+  int T[8], U[8];
+#pragma unroll
+  for (int xy = 0; xy < 4; ++xy) {  // k: rho(1) = R, rho(0) = 2P - R
+    T[2 * xy + 1] = S[2 * xy];
+    T[2 * xy] = 2 * S[2 * xy + 1] - S[2 * xy];
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)  // j: rho(1) = D + P, rho(0) = P - D
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      U[4 * x + 2 + c] = T[4 * x + c] + T[4 * x + 2 + c];
+      U[4 * x + c] = T[4 * x + 2 + c] - T[4 * x + c];
+    }
+#pragma unroll
+  for (int bc = 0; bc < 4; ++bc) {  // i: rho(1) = R, rho(0) = 2P - R
+    t[4 + bc] = U[bc];
+    t[bc] = 2 * U[4 + bc] - U[bc];
+  }
+}
+
+__device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j, int64_t row0,
+                                                int64_t col0, const uint8_t* const (&pa)[WI],
+                                                const uint8_t* const (&pk)[WK],
+                                                const uint8_t* pj,
+                                                u4 (*stage)[WI + WK + 1][64]) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, rl = lane & 15;
+  const int64_t n = a.n;
+  v4f acc[WI][WK][8];
+#pragma unroll
+  for (int m = 0; m < WI; ++m)
+#pragma unroll
+    for (int c = 0; c < WK; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[m][c][e] = v4f{0, 0, 0, 0};
+
+  auto body = [&](const u4 (&xa)[WI], const u4 (&xk)[WK], const u4& xj) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      unsigned y[4], sg[4], pm[4];
+      j_masks_f4(word_of(xj, 2 * h), y, sg, pm);
+      j_masks_f4(word_of(xj, 2 * h + 1), y + 2, sg + 2, pm + 2);
+      v8i AR[WI], AP[WI];
+#pragma unroll
+      for (int m = 0; m < WI; ++m) {
+        unsigned r0[2], p0[2], r1[2], p1[2];
+        tile2::planes16_f4(word_of(xa[m], 2 * h), r0, p0);
+        tile2::planes16_f4(word_of(xa[m], 2 * h + 1), r1, p1);
+        AR[m] = tile2::operand_f4(r0, r1);
+        AP[m] = tile2::operand_f4(p0, p1);
+      }
+#pragma unroll
+      for (int c = 0; c < WK; ++c) {
+        unsigned r0[2], p0[2], r1[2], p1[2];
+        tile2::planes16_f4(word_of(xk[c], 2 * h), r0, p0);
+        tile2::planes16_f4(word_of(xk[c], 2 * h + 1), r1, p1);
+        const unsigned R[4] = {r0[0], r0[1], r1[0], r1[1]};
+        const unsigned P[4] = {p0[0], p0[1], p1[0], p1[1]};
+        v8i B[4];  // y z = D R, D P, P R, P P
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          B[0][q] = (int)mod_d(R[q], y[q], sg[q]);
+          B[1][q] = (int)mod_d(P[q], y[q], sg[q]);
+          B[2][q] = (int)(R[q] & pm[q]);
+          B[3][q] = (int)(P[q] & pm[q]);
+        }
+#pragma unroll
+        for (int yz = 0; yz < 4; ++yz)
+#pragma unroll
+          for (int q = 4; q < 8; ++q) B[yz][q] = 0;
+#pragma unroll
+        for (int m = 0; m < WI; ++m)
+#pragma unroll
+          for (int yz = 0; yz < 4; ++yz) {
+            acc[m][c][yz] = tile2::mfma_f4(AR[m], B[yz], acc[m][c][yz]);
+            acc[m][c][4 + yz] = tile2::mfma_f4(AP[m], B[yz], acc[m][c][4 + yz]);
+          }
+      }
+    }
+  };
+
+  // Whole super-steps through the LDS stage (stage rows: k rows, i rows, j),
+  // then the masked tail from plain loads.
+  const int64_t nfull = a.n_f / 256;
+  auto issue = [&](int64_t st, int buf) {
+#pragma unroll
+    for (int c = 0; c < WK; ++c) tile2::stage_row(pk[c] + st * 64, &stage[buf][c][0]);
+#pragma unroll
+    for (int m = 0; m < WI; ++m) tile2::stage_row(pa[m] + st * 64, &stage[buf][WK + m][0]);
+    tile2::stage_row(pj + st * 64, &stage[buf][WK + WI][0]);
+  };
+  if (nfull > 0) issue(0, 0);
+  for (int64_t st = 0; st < nfull; ++st) {
+    const int buf = (int)(st & 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's rows are in LDS
+    u4 xa[WI], xk[WK];
+#pragma unroll
+    for (int c = 0; c < WK; ++c) xk[c] = stage[buf][c][lane];
+#pragma unroll
+    for (int m = 0; m < WI; ++m) xa[m] = stage[buf][WK + m][lane];
+    const u4 xj = stage[buf][WK + WI][lane];
+    if (st + 1 < nfull) issue(st + 1, buf ^ 1);
+    body(xa, xk, xj);
+  }
+  if (nfull * 256 < a.n_f) {
+    const int64_t kb = nfull * 64 + 16 * g;
+    u4 xa[WI], xk[WK];
+#pragma unroll
+    for (int m = 0; m < WI; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
+#pragma unroll
+    for (int c = 0; c < WK; ++c) xk[c] = load_fields64(pk[c] - 16 * g, kb, a.n_f);
+    body(xa, xk, load_fields64(pj - 16 * g, kb, a.n_f));
+  }
+
+  double wj[2], wk[WK][2];
+  triple_factors(a, j, wj);
+#pragma unroll
+  for (int c = 0; c < WK; ++c) triple_factors(a, col0 + 16 * c + rl, wk[c]);
+#pragma unroll
+  for (int m = 0; m < WI; ++m)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = row0 + 16 * m + 4 * g + e;
+      double wi[2];
+      triple_factors(a, i, wi);
+#pragma unroll
+      for (int c = 0; c < WK; ++c) {
+        const int64_t k = col0 + 16 * c + rl;
+        int S[8], t[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) S[x] = tile2::f4_count(acc[m][c][x][e]);
+        table3_f4(S, t);
+        emit_triple(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c]);
+      }
+    }
+}
+
 // General unit, one wave: the (16 WI) x (16 WK) tile of (i, k) at rows row0..,
-// columns col0.. for middle vector j, eight MFMA planes.
+// columns col0.. for middle vector j, eight MFMA planes.  fp4 form: the rows
+// of the next super-step travel into this wave's LDS stage (two buffers of
+// WK + WI + 1 rows) while the current one is multiplied.
+template <bool F4>
 __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, int64_t row0,
-                                             int64_t col0) {
+                                             int64_t col0, u4 (*stage)[WI + WK + 1][64]) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
   const int64_t n = a.n;
@@ -84,6 +266,11 @@ __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, in
     pk[c] = a.v + (rr < n ? rr : n - 1) * a.ld + 16 * g;
   }
   const uint8_t* pj = a.v + j * a.ld + 16 * g;
+
+  if constexpr (F4) {
+    general_wave_f4(a, j, row0, col0, pa, pk, pj, stage);
+    return;
+  }
 
   v4i acc[WI][WK][8];
 #pragma unroll
@@ -189,6 +376,9 @@ __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, in
 // Complete-data unit (see the notes at the top): all four waves build the
 // same 64 x 64 tile of S_xyz over a quarter of the 256-field super-steps
 // each, the partial sums meet in LDS, and wave w finishes rows 16w..16w+15.
+// fp4 form: rho_j(1) = 1 + D_j on every field of complete data, so
+// S_xyz = G[i][k] + sum rho_i(1) D_j rho_k(1): one plane, modulated by D_j.
+template <bool F4>
 __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, int64_t i0,
                                               int64_t k0, v4i (*part)[16][64]) {
 #pragma clang fp contract(off)
@@ -206,11 +396,42 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
   }
   const uint8_t* pj = a.v + j * a.ld + 16 * g;
 
-  v4i acc[4][4];
+  using Acc = std::conditional_t<F4, v4f, v4i>;
+  Acc acc[4][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[m][c] = v4i{0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) acc[m][c] = Acc{0, 0, 0, 0};
+
+  // fp4 step; `complete`: no padding code in the step's words
+  auto body_f4 = [&](auto& acc4, const u4 (&xa)[4], const u4 (&xk)[4], const u4& xj,
+                     auto complete) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      unsigned y[4], sg[4];
+      j_masks_f4(word_of(xj, 2 * h), y, sg, nullptr);
+      j_masks_f4(word_of(xj, 2 * h + 1), y + 2, sg + 2, nullptr);
+      v8i A[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        A[m] = tile2::nibbles32(tile2::rho1_16_f4<complete.value>(word_of(xa[m], 2 * h)),
+                                tile2::rho1_16_f4<complete.value>(word_of(xa[m], 2 * h + 1)));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const unsigned z0 = tile2::rho1_16_f4<complete.value>(word_of(xk[c], 2 * h));
+        const unsigned z1 = tile2::rho1_16_f4<complete.value>(word_of(xk[c], 2 * h + 1));
+        const unsigned R[4] = {z0 & tile2::kNib2, (z0 >> 2) & tile2::kNib2, z1 & tile2::kNib2,
+                               (z1 >> 2) & tile2::kNib2};
+        v8i B;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B[q] = (int)mod_d(R[q], y[q], sg[q]);
+#pragma unroll
+        for (int q = 4; q < 8; ++q) B[q] = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc4[m][c] = tile2::mfma_f4(A[m], B, acc4[m][c]);
+      }
+    }
+  };
 
   const int64_t steps = (a.n_f + 255) / 256;
   const int64_t s_end = steps * (wave + 1) / 4;
@@ -232,6 +453,13 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
         xk[m] = load_fields64(pk[m] - 16 * g, kb + 16 * g, a.n_f);
       }
       xj = load_fields64(pj - 16 * g, kb + 16 * g, a.n_f);
+    }
+    if constexpr (F4) {
+      if (full)
+        body_f4(acc, xa, xk, xj, std::true_type{});
+      else
+        body_f4(acc, xa, xk, xj, std::false_type{});
+      continue;
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -260,7 +488,15 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) part[wave][4 * m + c][lane] = acc[m][c];
+    for (int c = 0; c < 4; ++c) {
+      if constexpr (F4) {
+        const v4f x = acc[m][c];
+        part[wave][4 * m + c][lane] = v4i{tile2::f4_count(x[0]), tile2::f4_count(x[1]),
+                                          tile2::f4_count(x[2]), tile2::f4_count(x[3])};
+      } else {
+        part[wave][4 * m + c][lane] = acc[m][c];
+      }
+    }
   __syncthreads();
 
   // Rows i0 + 16 wave + 4g + e, columns k0 + 16c + rl.
@@ -297,7 +533,8 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
       const bool valid = k > j && k < n && i < j;
       const int64_t kk = k > j && k < n ? k : j;
       const unsigned XZ = (unsigned)grow_i[kk - g0];
-      const unsigned XYZ = (unsigned)xyz[c][e];
+      // fp4: the partial sums hold sum rho_i(1) D_j rho_k(1)
+      const unsigned XYZ = F4 ? XZ + (unsigned)xyz[c][e] : (unsigned)xyz[c][e];
       int t[8];
       t[7] = (int)XYZ;
       t[6] = (int)(2u * XY - XYZ);
@@ -312,10 +549,14 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
   }
 }
 
+template <bool F4>
 __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid ug,
                                                        const int64_t* __restrict__ offs,
                                                        int64_t unit_base, int64_t count) {
+  // 64 KB: the complete-data partial tiles, or else each wave's two fp4 stage
+  // buffers of WK + WI + 1 rows
   __shared__ v4i part[4][16][64];
+  static_assert(sizeof(part) >= 4 * 2 * (WI + WK + 1) * 64 * sizeof(u4), "stage buffers fit");
   const int wave = threadIdx.x >> 6;
   const int64_t n = a.n;
   const int64_t u = unit_base + xcd_unit(blockIdx.x, count);
@@ -330,7 +571,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid u
     r = r < n ? r : n - 1;
     const bool ok = reinterpret_cast<const v4i*>(a.counts)[r].z == a.n_f;
     if (__syncthreads_and(ok ? 1 : 0)) {
-      complete_unit(a, j, it * BI, kt * BK, part);
+      complete_unit<F4>(a, j, it * BI, kt * BK, part);
       return;
     }
   }
@@ -338,7 +579,8 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid u
   const int64_t row0 = it * BI + (wave & 1) * 16 * WI;  // i range of this wave
   const int64_t col0 = kt * BK + (wave >> 1) * 16 * WK; // k range of this wave
   if (row0 >= j || col0 + 16 * WK - 1 <= j || col0 >= n) return;
-  general_wave(a, j, row0, col0);
+  general_wave<F4>(a, j, row0, col0,
+                   reinterpret_cast<u4(*)[WI + WK + 1][64]>(&part[0][0][0]) + 2 * wave);
 }
 
 // G[r][c] = sum_q rho_{g0+r,q}(1) rho_{g0+c,q}(1) for r, c < ng: the pair
@@ -393,7 +635,8 @@ hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return launch_units(mfma3_kernel, a, BI, "mfma3", stream);
+  if (a.n_f <= kF4MaxFields) return launch_units(mfma3_kernel<true>, a, BI, "mfma3", stream);
+  return launch_units(mfma3_kernel<false>, a, BI, "mfma3", stream);
 }
 
 }  // namespace ccc

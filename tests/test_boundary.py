@@ -30,11 +30,11 @@ def test_status_strings_and_version():
 
 def test_two_way_operand_format_query():
     # fp4 while every accumulated quarter-multiple (at most n_f) is exact in fp32
-    assert ccc.two_way_operands(0) == "fp4"
-    assert ccc.two_way_operands(65536) == "fp4"
-    assert ccc.two_way_operands(1 << 22) == "fp4"
-    assert ccc.two_way_operands((1 << 22) + 1) == "int8"
-    assert ccc.lib().ccc_2way_operands(-1) == ccc.CCC_ERR_ARG
+    assert ccc.mfma_operands(0) == "fp4"
+    assert ccc.mfma_operands(65536) == "fp4"
+    assert ccc.mfma_operands(1 << 22) == "fp4"
+    assert ccc.mfma_operands((1 << 22) + 1) == "int8"
+    assert ccc.lib().ccc_mfma_operands(-1) == ccc.CCC_ERR_ARG
 
 
 def test_default_opts():
