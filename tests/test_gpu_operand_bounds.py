@@ -73,3 +73,24 @@ def test_batch_mixing_sizes_across_the_fp4_bound(big):
         ot, oc = oracle.two_way(v, n_f)
         assert_tables_equal(host(t), ot)
         assert_ccc_close(host(c), oc)
+
+
+@pytest.mark.parametrize("complete", [False, True])
+@pytest.mark.parametrize("n_f", [LIMIT, LIMIT + 1])
+def test_3way_on_both_sides_of_the_fp4_bound(n_f, complete):
+    """Three all-11 rows put C(1,1,1) at 8 n_f; with no missing entry every
+    unit takes the one-plane complete-data form (its Gram pair sums too)."""
+    say("fp4 bound 3-way", n_f, complete)
+    if complete:
+        v = np.ascontiguousarray(np.concatenate([
+            synth.constant([3, 3, 3, 0, 1], n_f, seed=4),
+            synth.beta_hw(3, n_f, seed=5, missing=0.0)]))
+    else:
+        v = np.ascontiguousarray(np.concatenate([synth.constant([3], n_f, seed=4),
+                                                 extreme_rows(n_f, seed=6)]))
+    t, c, _ = ccc.ccc_3way(dev(v), n_f, path="mfma")
+    sync()
+    ot, oc = oracle.three_way(v, n_f)
+    assert_tables_equal(host(t), ot)
+    assert_ccc_close(host(c), oc)
+    assert int(ot.max()) == 8 * n_f
