@@ -34,8 +34,8 @@ FP4_PEAK_TFLOPS = 10100.0    # MI355X dense fp4 (e2m1) MFMA, 10.1 PFLOP/s
 
 
 def mfma_format(n_f):
-    """(operand format, dense peak in T(FL)OP/s, dtype tag) of the 2-way and
-    3-way MFMA kernels over n_f fields, as the library reports it."""
+    """(operand format, dense peak in T(FL)OP/s, dtype tag) of the MFMA kernels
+    over n_f fields, as the library reports it."""
     import paper_1705_08213_amd as ccc
     fmt = ccc.mfma_operands(n_f)
     return (fmt, FP4_PEAK_TFLOPS, "fp4") if fmt == "fp4" else (fmt, INT8_PEAK_TOPS, "i8")
@@ -66,8 +66,8 @@ def committed_traffic(kernel_sources, profile):
 
 MFMA2_SOURCES = ["paper_1705_08213_amd/csrc/mfma2.hip", "paper_1705_08213_amd/csrc/tile2.h",
                  "paper_1705_08213_amd/csrc/common.h", "paper_1705_08213_amd/csrc/kernels.h"]
-MULTI2_SOURCES = ["paper_1705_08213_amd/csrc/multi2.hip", "paper_1705_08213_amd/csrc/common.h",
-                  "paper_1705_08213_amd/csrc/kernels.h"]
+MULTI2_SOURCES = ["paper_1705_08213_amd/csrc/multi2.hip", "paper_1705_08213_amd/csrc/tile2.h",
+                  "paper_1705_08213_amd/csrc/common.h", "paper_1705_08213_amd/csrc/kernels.h"]
 MFMA3_SOURCES = ["paper_1705_08213_amd/csrc/mfma3.hip", "paper_1705_08213_amd/csrc/tile3.h",
                  "paper_1705_08213_amd/csrc/tile2.h", "paper_1705_08213_amd/csrc/common.h",
                  "paper_1705_08213_amd/csrc/kernels.h"]
@@ -304,24 +304,25 @@ def bench_multi(args, lib):
 
     ms, kms, _ = timed(step, args.steps, args.warmup, lib, "multi2")
     comps = P * n_f
-    ops = 2.0 * s * s * comps  # s^2 int8 MACs per comparison
+    ops = 2.0 * s * s * comps  # s^2 MACs per comparison
     ach = ops / (kms / 1e3) / 1e12
+    fmt, peak, dt = mfma_format(n_f)
     out = dict(metric="CCC comparisons/sec (pairs*n_f), bit-exact tables", value=comps / (ms / 1e3),
                unit="comparisons/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="i8", data="synthetic",
+               dtype=dt, data="synthetic",
                config=dict(workload=f"2-way multi-allelic CCC: n_v={n_v} x n_f={n_f}, s={s} "
                                     "states, normalised sin^2 frequencies / Hardy-Weinberg, "
                                     "1% missing", n_v=n_v, n_f=n_f, states=s, missing=missing,
-                           path="mfma"),
-               roofline=dict(bound="mfma", achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s",
-                             frac=ach / INT8_PEAK_TOPS,
+                           path="mfma", operands=fmt),
+               roofline=dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                             frac=ach / peak, operands=fmt,
                              traffic=committed_traffic(MULTI2_SOURCES,
                                                        "profiles/multi2_2way_n16384_f32768_s4.md"),
                              traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                              algorithmic_bytes=n_v * n_f + P * s * s * 12 + 32 * n_v,
                              kernel="multi2_kernel", kernel_ms=kms,
-                             int8_ops_per_comparison=int(2 * s * s)))
+                             ops_per_comparison=int(2 * s * s)))
     if not args.no_cpu:
         import oracle
         rows, pairs, dt = oracle_sample(lambda r0, r1: oracle.multi_two_way(v, n_f, s, r0, r1),

@@ -81,21 +81,21 @@ enum {
 };
 
 /*
- * Operand formats of the MFMA path.  The 2-way and 3-way calls (ccc_2way,
- * ccc_3way and their _rows, _select, _block and _many forms) take fp4 (e2m1)
- * operands with fp32 accumulation while n_f <= 2^22 (a batch of
+ * Operand formats of the MFMA path.  Every MFMA call (ccc_2way, ccc_3way,
+ * their _rows, _select, _block and _many forms, and ccc_2way_multi) takes
+ * fp4 (e2m1) operands with fp32 accumulation while n_f <= 2^22 (a batch of
  * ccc_2way_many: while every problem's n_f is), int8 operands with int32
  * accumulation beyond.  The fp4 operands are per-allele planes halved
- * (rho(1)/2, P/2 with P = 1 for a present entry, and for the 3-way middle
+ * (rho(a)/2, P/2 with P = 1 for a present entry, and for the 3-way middle
  * vector (rho(1) - P)/2), values 0, +-1/2 and 1, each exact in e2m1; every
  * partial sum is a multiple of 1/4 of magnitude at most n_f, so below 2^22
  * fp32 holds it exactly and the tables are the same exact integers as with
- * int8.  The multi-allelic call uses int8.
+ * int8.
  */
 enum { CCC_OPERANDS_FP4 = 4, CCC_OPERANDS_INT8 = 8 };
 
-/* CCC_OPERANDS_* of a 2-way or 3-way MFMA call over n_f fields (host only,
- * no device work); CCC_ERR_ARG for n_f < 0. */
+/* CCC_OPERANDS_* of an MFMA call over n_f fields (host only, no device
+ * work); CCC_ERR_ARG for n_f < 0. */
 int ccc_mfma_operands(int64_t n_f);
 
 /* Flags for ccc_2way_block (field-chunked use). */

@@ -106,7 +106,7 @@ def version() -> int:
 
 
 def mfma_operands(n_f: int) -> str:
-    """Operand format of a 2-way or 3-way MFMA call over n_f fields: "fp4" or "int8"."""
+    """Operand format of an MFMA call over n_f fields: "fp4" or "int8"."""
     r = lib().ccc_mfma_operands(n_f)
     _raise(r if r < 0 else 0, "ccc_mfma_operands")
     return {4: "fp4", 8: "int8"}[r]

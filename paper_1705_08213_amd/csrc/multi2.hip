@@ -1,4 +1,4 @@
-// multi2.hip -- multi-allelic 2-way tallies and CCC on the int8 matrix cores
+// multi2.hip -- multi-allelic 2-way tallies and CCC on the matrix cores
 // (markers with s = 2..4 states: the s x s table of relationships of the
 // paper's stated extension, Sec. 7 item 2, with the Sec. 2.1 definitions
 // taken over the state set {0, .., s-1}).
@@ -22,8 +22,18 @@
 // Epilogue: m_ij = sum_ab C(a,b) / 4; CCC(a,b) = C/(4 m_ij) * w_i(a) * w_j(b)
 // with the per-vector factors w(a) = 1 - gamma n(a)/(2m) computed once per
 // row and column, and the quotient corrected to the rounded C/(4 m_ij).
-#include "common.h"
-#include "kernels.h"
+//
+// fp4 form (n_f <= kF4MaxFields): the 16x16x128 scaled MFMA with e2m1 operands
+// rho(a)/2 (values 0, 1/2, 1; sums of quarter-multiples at most n_f, exact in
+// fp32).  A lane holds 32 fields of a row per MFMA step: the 32 bytes at 32 g
+// of each 128-field step, as two 16-byte pieces; operand register r takes
+// state a of piece 0's word r (4 fields) in its low nibbles and of piece 1's
+// word r in its high nibbles, 3-4 VALU ops per 8 fields.  The next step's
+// pieces travel from memory into the wave's LDS stage while the current step
+// is multiplied.
+#include <type_traits>
+
+#include "tile2.h"
 
 namespace ccc {
 
@@ -58,6 +68,29 @@ __device__ __forceinline__ u4 load_bytes16(const uint8_t* __restrict__ row, int6
 __device__ __forceinline__ v4i state_plane(const u4& w, int a) {
   return v4i{(int)((w.x >> (2 * a)) & kLow2), (int)((w.y >> (2 * a)) & kLow2),
              (int)((w.z >> (2 * a)) & kLow2), (int)((w.w >> (2 * a)) & kLow2)};
+}
+
+// State a of 8 fields (word r of two pieces) as 8 e2m1 nibbles.
+template <int A>
+__device__ __forceinline__ unsigned state_nibbles(unsigned lo, unsigned hi) {
+  constexpr unsigned kLo = 0x03030303u, kHi = 0x30303030u;
+  const unsigned l = (lo >> (2 * A)) & kLo;
+  const unsigned h = (4 - 2 * A >= 0) ? (hi << (4 - 2 * A)) : (hi >> (2 * A - 4));
+  return (h & kHi) | l;
+}
+
+template <int A>
+__device__ __forceinline__ v8i state_operand_f4(const u4& p0, const u4& p1) {
+  return v8i{(int)state_nibbles<A>(p0.x, p1.x), (int)state_nibbles<A>(p0.y, p1.y),
+             (int)state_nibbles<A>(p0.z, p1.z), (int)state_nibbles<A>(p0.w, p1.w), 0, 0, 0, 0};
+}
+
+template <int S>
+__device__ __forceinline__ void state_operands_f4(const u4& p0, const u4& p1, v8i (&o)[S]) {
+  o[0] = state_operand_f4<0>(p0, p1);
+  o[1] = state_operand_f4<1>(p0, p1);
+  if constexpr (S > 2) o[2] = state_operand_f4<2>(p0, p1);
+  if constexpr (S > 3) o[3] = state_operand_f4<3>(p0, p1);
 }
 
 // Sum of the 4 bytes of x when each is at most 63.
@@ -156,24 +189,32 @@ __device__ __forceinline__ void multi_store(const Multi2Args& a, int64_t p,
   }
 }
 
-template <int S>
+template <int S, bool F4 = false>
 struct MultiShape;
 template <>
-struct MultiShape<2> {
+struct MultiShape<2, false> {
   static constexpr int WM = 4, WN = 2, U = 1;
 };
+// fp4, s = 2: the 4 x 2 tile needs more than the 256 registers of two waves
+// per SIMD once its operands are nibbles, so it takes the s = 3 shape
 template <>
-struct MultiShape<3> {
+struct MultiShape<2, true> {
+  static constexpr int WM = 2, WN = 2;
+};
+template <int S>
+struct MultiShape<S, true> : MultiShape<S, false> {};
+template <>
+struct MultiShape<3, false> {
   static constexpr int WM = 2, WN = 2, U = 1;
 };
 template <>
-struct MultiShape<4> {
+struct MultiShape<4, false> {
   static constexpr int WM = 2, WN = 1, U = 2;
 };
 
-template <int S>
+template <int S, bool F4>
 __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t tiles_side) {
-  constexpr int WM = MultiShape<S>::WM, WN = MultiShape<S>::WN;
+  constexpr int WM = MultiShape<S, F4>::WM, WN = MultiShape<S, F4>::WN;
   constexpr int BM = 32 * WM, BN = 32 * WN, PARTS = BM / BN;
   static_assert(BM % BN == 0, "square tiles split into whole column parts");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -199,13 +240,77 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
     pb[n] = a.v + (r < a.n ? r : a.n - 1) * a.ld + 16 * g;
   }
 
-  v4i acc[WM][WN][S * S];
+  using Acc = std::conditional_t<F4, v4f, v4i>;
+  Acc acc[WM][WN][S * S];
 #pragma unroll
   for (int m = 0; m < WM; ++m)
 #pragma unroll
     for (int n = 0; n < WN; ++n)
 #pragma unroll
-      for (int x = 0; x < S * S; ++x) acc[m][n][x] = v4i{0, 0, 0, 0};
+      for (int x = 0; x < S * S; ++x) acc[m][n][x] = Acc{0, 0, 0, 0};
+
+  if constexpr (F4) {
+    // fp4: 128-field steps; lane group g holds bytes [32 g, 32 g + 32) of each
+    __shared__ u4 stage_all[4][2][2 * (WM + WN)][64];
+    u4(*stage)[2 * (WM + WN)][64] = stage_all[wave];
+    const uint8_t* qa[WM];
+    const uint8_t* qb[WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m) qa[m] = pa[m] + 16 * g;  // row + 32 g
+#pragma unroll
+    for (int n = 0; n < WN; ++n) qb[n] = pb[n] + 16 * g;
+    // row(side, r, h) gives piece h of row r of side 0 (A) or 1 (B)
+    auto step = [&](auto row) {
+      v8i B[WN][S];
+#pragma unroll
+      for (int n = 0; n < WN; ++n) state_operands_f4<S>(row(1, n, 0), row(1, n, 1), B[n]);
+#pragma unroll
+      for (int m = 0; m < WM; ++m) {
+        v8i A[S];
+        state_operands_f4<S>(row(0, m, 0), row(0, m, 1), A);
+#pragma unroll
+        for (int n = 0; n < WN; ++n)
+#pragma unroll
+          for (int x = 0; x < S * S; ++x)
+            acc[m][n][x] = tile2::mfma_f4(A[x / S], B[n][x % S], acc[m][n][x]);
+      }
+    };
+    const int64_t nfull = a.n_f / 128;
+    auto issue = [&](int64_t st, int buf) {
+#pragma unroll
+      for (int n = 0; n < WN; ++n)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          tile2::stage_row(qb[n] + st * 128 + 16 * h, &stage[buf][2 * n + h][0]);
+#pragma unroll
+      for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          tile2::stage_row(qa[m] + st * 128 + 16 * h, &stage[buf][2 * (WN + m) + h][0]);
+    };
+    if (nfull > 0) issue(0, 0);
+    for (int64_t st = 0; st < nfull; ++st) {
+      const int buf = (int)(st & 1);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's pieces are in LDS
+      if (st + 1 < nfull) issue(st + 1, buf ^ 1);
+      step([&](int side, int r, int h) -> u4 {
+        return stage[buf][2 * (side ? r : WN + r) + h][lane];
+      });
+    }
+    if (nfull * 128 < a.n_f) {
+      const int64_t kb = nfull * 128 + 32 * g;
+      u4 xa[WM][2], xb[WN][2];
+#pragma unroll
+      for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) xa[m][h] = load_bytes16(qa[m] - 32 * g, kb + 16 * h, a.n_f);
+#pragma unroll
+      for (int n = 0; n < WN; ++n)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) xb[n][h] = load_bytes16(qb[n] - 32 * g, kb + 16 * h, a.n_f);
+      step([&](int side, int r, int h) -> u4 { return side ? xb[r][h] : xa[r][h]; });
+    }
+  } else {
 
   auto step = [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
     v4i A[WM][S], B[WN][S];
@@ -230,7 +335,7 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
   // 64-field steps in groups of U: plain 16-byte loads of the next group are
   // issued before the current group's MFMAs while the steps are whole; then
   // the whole steps left over, and one masked step for the tail.
-  constexpr int U = MultiShape<S>::U;
+  constexpr int U = MultiShape<S, F4>::U;
   const int64_t nfull = a.n_f / 64, ngroups = nfull / U;
   u4 ca[U][WM], cb[U][WN];
   auto load_group = [&](int64_t st0, u4 (&xa)[U][WM], u4 (&xb)[U][WN]) {
@@ -272,6 +377,8 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
     step(ca[0], cb[0]);
   }
 
+  }
+
   // Epilogue: lane holds rows 4g + e of column rl of each 16x16 block.
   const bool want_w = a.ccc != nullptr;
 #pragma unroll
@@ -289,23 +396,34 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
         if (want_w) multi_factors<S>(a, i, wi);
         int t[S * S];
 #pragma unroll
-        for (int x = 0; x < S * S; ++x) t[x] = acc[m][n][x][e];
+        for (int x = 0; x < S * S; ++x) {
+          if constexpr (F4)
+            t[x] = tile2::f4_count(acc[m][n][x][e]);
+          else
+            t[x] = acc[m][n][x][e];
+        }
         multi_store<S>(a, pair_index(a.n, i, j), t, wi, wj);
       }
   }
 }
 
-template <int S>
-hipError_t launch_multi2_s(const Multi2Args& a, hipStream_t stream) {
-  constexpr int BM = 32 * MultiShape<S>::WM, BN = 32 * MultiShape<S>::WN;
+template <int S, bool F4>
+hipError_t launch_multi2_shape(const Multi2Args& a, hipStream_t stream) {
+  constexpr int BM = 32 * MultiShape<S, F4>::WM, BN = 32 * MultiShape<S, F4>::WN;
   const int64_t T = (a.n + BM - 1) / BM;
   const int64_t ntiles = (BM / BN) * (T * (T + 1) / 2);
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   timing_begin("multi2", stream);
-  hipLaunchKernelGGL(multi2_kernel<S>, dim3((unsigned)ntiles), dim3(256), 0, stream, a, T);
+  hipLaunchKernelGGL((multi2_kernel<S, F4>), dim3((unsigned)ntiles), dim3(256), 0, stream, a, T);
   timing_end(stream);
   return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_multi2_s(const Multi2Args& a, hipStream_t stream) {
+  return a.n_f <= kF4MaxFields ? launch_multi2_shape<S, true>(a, stream)
+                               : launch_multi2_shape<S, false>(a, stream);
 }
 
 }  // namespace
