@@ -225,7 +225,10 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
   tri_tile(b / PARTS, tiles_side, sq_i, sq_j);
   const int64_t row0 = sq_i * BM + (wave & 1) * 16 * WM;
   const int64_t col0 = (sq_j * PARTS + b % PARTS) * BN + (wave >> 1) * 16 * WN;
-  if (row0 >= a.n || col0 >= a.n || row0 >= col0 + 16 * WN - 1) return;  // no pair i < j
+  // a wave with no pair i < j does no MFMA work (in the fp4 form it still
+  // shares the workgroup's loads and barriers)
+  const bool active = !(row0 >= a.n || col0 >= a.n || row0 >= col0 + 16 * WN - 1);
+  if (!F4 && !active) return;
 
   const uint8_t* pa[WM];
   const uint8_t* pb[WN];
@@ -251,15 +254,24 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
 
   if constexpr (F4) {
     // fp4: 128-field steps; lane group g holds bytes [32 g, 32 g + 32) of each
-    __shared__ u4 stage_all[4][2][2 * (WM + WN)][64];
-    u4(*stage)[2 * (WM + WN)][64] = stage_all[wave];
-    const uint8_t* qa[WM];
-    const uint8_t* qb[WN];
+    // row's step as two 16-byte pieces.  The workgroup's 2 WM + 2 WN row
+    // blocks are copied into LDS once per step (the four waves share the
+    // 2 (2 WM + 2 WN) piece copies), double-buffered, one barrier per step;
+    // each wave then reads its own WM + WN blocks from there.
+    constexpr int NB = 2 * WM + 2 * WN, ND = 2 * NB, DPW = ND / 4;
+    static_assert(ND % 4 == 0, "the piece copies split evenly over the waves");
+    __shared__ u4 stage[2][ND][64];  // piece 2 blk + h; A blocks first, then B
+    const int64_t I0 = sq_i * BM, J0 = (sq_j * PARTS + b % PARTS) * BN;
+    const uint8_t* src[DPW];
 #pragma unroll
-    for (int m = 0; m < WM; ++m) qa[m] = pa[m] + 16 * g;  // row + 32 g
-#pragma unroll
-    for (int n = 0; n < WN; ++n) qb[n] = pb[n] + 16 * g;
-    // row(side, r, h) gives piece h of row r of side 0 (A) or 1 (B)
+    for (int q = 0; q < DPW; ++q) {
+      const int d = wave + 4 * q, blk = d >> 1, h = d & 1;
+      int64_t r = blk < 2 * WM ? I0 + 16 * blk + rl : J0 + 16 * (blk - 2 * WM) + rl;
+      r = r < a.n ? r : a.n - 1;
+      src[q] = a.v + r * a.ld + 32 * g + 16 * h;
+    }
+    const int ablk = (wave & 1) * WM, bblk = 2 * WM + (wave >> 1) * WN;
+    // row(side, r, h) gives piece h of this wave's row block r of side 0 (A) or 1 (B)
     auto step = [&](auto row) {
       v8i B[WN][S];
 #pragma unroll
@@ -278,36 +290,31 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
     const int64_t nfull = a.n_f / 128;
     auto issue = [&](int64_t st, int buf) {
 #pragma unroll
-      for (int n = 0; n < WN; ++n)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          tile2::stage_row(qb[n] + st * 128 + 16 * h, &stage[buf][2 * n + h][0]);
-#pragma unroll
-      for (int m = 0; m < WM; ++m)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          tile2::stage_row(qa[m] + st * 128 + 16 * h, &stage[buf][2 * (WN + m) + h][0]);
+      for (int q = 0; q < DPW; ++q) tile2::stage_row(src[q] + st * 128, &stage[buf][wave + 4 * q][0]);
     };
     if (nfull > 0) issue(0, 0);
     for (int64_t st = 0; st < nfull; ++st) {
       const int buf = (int)(st & 1);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's pieces are in LDS
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's copies landed
+      __syncthreads();  // every wave's copies landed; the other buffer is no longer read
       if (st + 1 < nfull) issue(st + 1, buf ^ 1);
-      step([&](int side, int r, int h) -> u4 {
-        return stage[buf][2 * (side ? r : WN + r) + h][lane];
-      });
+      if (active)
+        step([&](int side, int r, int h) -> u4 {
+          return stage[buf][2 * (side ? bblk + r : ablk + r) + h][lane];
+        });
     }
+    if (!active) return;
     if (nfull * 128 < a.n_f) {
       const int64_t kb = nfull * 128 + 32 * g;
       u4 xa[WM][2], xb[WN][2];
 #pragma unroll
       for (int m = 0; m < WM; ++m)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) xa[m][h] = load_bytes16(qa[m] - 32 * g, kb + 16 * h, a.n_f);
+        for (int h = 0; h < 2; ++h) xa[m][h] = load_bytes16(pa[m] - 16 * g, kb + 16 * h, a.n_f);
 #pragma unroll
       for (int n = 0; n < WN; ++n)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) xb[n][h] = load_bytes16(qb[n] - 32 * g, kb + 16 * h, a.n_f);
+        for (int h = 0; h < 2; ++h) xb[n][h] = load_bytes16(pb[n] - 16 * g, kb + 16 * h, a.n_f);
       step([&](int side, int r, int h) -> u4 { return side ? xb[r][h] : xa[r][h]; });
     }
   } else {

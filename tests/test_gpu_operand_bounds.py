@@ -94,3 +94,25 @@ def test_3way_on_both_sides_of_the_fp4_bound(n_f, complete):
     assert_tables_equal(host(t), ot)
     assert_ccc_close(host(c), oc)
     assert int(ot.max()) == 8 * n_f
+
+
+@pytest.mark.parametrize("n_f", [LIMIT, LIMIT + 1])
+def test_multi_allelic_on_both_sides_of_the_fp4_bound(n_f):
+    """s = 4: two rows homozygous for state 3 (byte 0x80: rho(3) = 2) put
+    C(3,3) at 4 n_f; a row homozygous for state 0 (0x02), random rows with
+    and without missing entries."""
+    s = 4
+    say("fp4 bound multi", n_f)
+    rand = synth.multi_hw(4, n_f, s, seed=8, missing=0.01)
+    ld = rand.shape[1]
+    const = np.zeros((3, ld), dtype=np.uint8)
+    const[0, :n_f] = 0x80
+    const[1, :n_f] = 0x80
+    const[2, :n_f] = 0x02
+    v = np.ascontiguousarray(np.concatenate([const, rand]))
+    t, c, _ = ccc.ccc_2way_multi(dev(v), n_f, s)
+    sync()
+    ot, oc = oracle.multi_two_way(v, n_f, s)
+    assert_tables_equal(host(t), ot)
+    assert_ccc_close(host(c), oc)
+    assert int(ot.max()) == 4 * n_f
