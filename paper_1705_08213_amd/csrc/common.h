@@ -129,13 +129,15 @@ __device__ __forceinline__ void pair_ccc(v4i t, const double (&wi)[2], const dou
 __device__ __forceinline__ void store_pair(int64_t p, v4i t, const double (&wi)[2],
                                            const double (&wj)[2], int32_t* __restrict__ tables,
                                            double* __restrict__ ccc) {
-  if (tables) *reinterpret_cast<v4i*>(tables + 4 * p) = t;
+  // streaming stores: the dense output is written once and not read back here
+  if (tables) __builtin_nontemporal_store(t, reinterpret_cast<v4i*>(tables + 4 * p));
   if (ccc) {
     double r[4];
     pair_ccc(t, wi, wj, r);
-    double2* out = reinterpret_cast<double2*>(ccc + 4 * p);
-    out[0] = double2{r[0], r[1]};
-    out[1] = double2{r[2], r[3]};
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2* out = reinterpret_cast<d2*>(ccc + 4 * p);
+    __builtin_nontemporal_store(d2{r[0], r[1]}, out);
+    __builtin_nontemporal_store(d2{r[2], r[3]}, out + 1);
   }
 }
 
