@@ -178,6 +178,8 @@ int two_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_be
   a.ccc = ccc;
   a.counts_a = cnt;
   a.counts_b = cnt;
+  a.chunk_a = cnt;
+  a.chunk_b = cnt;
   a.gamma = o.gamma;
   a.row_begin = i_begin;
   a.row_end = row_end;
@@ -320,6 +322,18 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   if (!aligned16(tables) || !aligned16(ccc) || !aligned16(counts_a) || !aligned16(counts_b))
     return CCC_ERR_ALIGN;
   if (n_a == 0 || n_b == 0) return CCC_OK;
+  // an accumulating call also needs this chunk's own counts (workspace)
+  int32_t* chunk_a = counts_a;
+  int32_t* chunk_b = counts_b;
+  if (acc) {
+    void* ws = nullptr;
+    if ((st = ccc::workspace((size_t)(n_a + n_b) * 16, &ws))) return st;
+    chunk_a = static_cast<int32_t*>(ws);
+    chunk_b = chunk_a + 4 * n_a;
+    if (ccc::launch_count1(va, lda, n_a, n_f, chunk_a, 0, stream) != hipSuccess ||
+        ccc::launch_count1(vb, ldb, n_b, n_f, chunk_b, 0, stream) != hipSuccess)
+      return CCC_ERR_HIP;
+  }
   if (ccc::launch_count1(va, lda, n_a, n_f, counts_a, acc, stream) != hipSuccess)
     return CCC_ERR_HIP;
   if (ccc::launch_count1(vb, ldb, n_b, n_f, counts_b, acc, stream) != hipSuccess)
@@ -334,6 +348,8 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   a.ccc = fin ? ccc : nullptr;
   a.counts_a = counts_a;
   a.counts_b = counts_b;
+  a.chunk_a = chunk_a;
+  a.chunk_b = chunk_b;
   a.gamma = o.gamma;
   a.row_begin = 0;
   a.row_end = n_a;

@@ -32,6 +32,10 @@ struct Pair2Args {
   double* ccc;                // may be null
   const int32_t* counts_a;    // [n_a][4]
   const int32_t* counts_b;    // [n_b][4]
+  // this call's own 1-way counts of its n_f fields (the same arrays as
+  // counts_a / counts_b unless accumulating, where those are running totals)
+  const int32_t* chunk_a;
+  const int32_t* chunk_b;
   double gamma;
   // rows of A whose pairs are produced; pair (i, j) goes to entry p(i,j) - p_base
   int64_t row_begin, row_end;

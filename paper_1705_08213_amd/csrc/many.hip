@@ -91,6 +91,8 @@ __device__ __forceinline__ Pair2Args pair_args(const ProbDesc& p, double gamma) 
   a.ccc = p.ccc;
   a.counts_a = p.counts;
   a.counts_b = p.counts;
+  a.chunk_a = p.counts;
+  a.chunk_b = p.counts;
   a.gamma = gamma;
   a.row_begin = 0;
   a.row_end = p.n_v;

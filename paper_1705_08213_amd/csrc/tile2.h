@@ -150,9 +150,10 @@ __device__ __forceinline__ void mma_superstep_rho1(const u4 (&pa)[WM], const u4 
 // order).  Products are multiples of 1/4 and a sum over n_f fields is at most
 // n_f, so fp32 accumulation is exact while n_f <= 2^22 (kF4MaxFields); the
 // four sums S = sum rho_i rho_j, T = sum rho_i P_j, U = sum P_i rho_j,
-// V = sum P_i P_j (each 4x the accumulated value) give the table:
+// V = sum P_i P_j give the table:
 //   C11 = S,  C10 = 2T - S,  C01 = 2U - S,  C00 = 4V - 2T - 2U + S
-// (rho(0) = 2P - rho(1)).  Fields past n_f carry the missing code, which is
+// (rho(0) = 2P - rho(1)); the general loop reaches them through the cheaper
+// plane X = rho(1) + missing (planes16_f4x).  Fields past n_f carry the missing code, which is
 // zero in both planes.
 // ---------------------------------------------------------------------------
 
@@ -169,6 +170,22 @@ __device__ __forceinline__ void planes16_f4(unsigned w, unsigned (&r)[2], unsign
   const unsigned r1 = (w & kEven2) + __builtin_amdgcn_bitop3_b32(w, s, kEven2, 0x80);
   r[0] = r1 & kNib2;
   r[1] = (r1 >> 2) & kNib2;
+  p[0] = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
+  p[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
+}
+
+// The 2-way planes X = lo + hi (= code - hi: rho(1), plus 1 on a missing or
+// padding field) and P, in nine operations.  rho(1) = X + P - 1, so with
+// K the fields a loop covers (padding included) and n(1), m this call's
+// counts, the sums XX, XY, YX, YY of X and P give
+//   S = XX + XY + YX + YY - n_i(1) - n_j(1) - K,   T = XY + YY - m_j,
+//   U = YX + YY - m_i,   V = YY
+// (sum_q X_i = n_i(1) + K - m_i and sum_q P_i = m_i over the K fields).
+__device__ __forceinline__ void planes16_f4x(unsigned w, unsigned (&r)[2], unsigned (&p)[2]) {
+  const unsigned s = w >> 1;
+  const unsigned x = w - (s & kEven2);
+  r[0] = x & kNib2;
+  r[1] = (x >> 2) & kNib2;
   p[0] = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
   p[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
 }
@@ -199,14 +216,19 @@ __device__ __forceinline__ v4f mfma_f4(const v8i& a, const v8i& b, v4f c) {
 
 __device__ __forceinline__ int f4_count(float x) { return (int)(4.0f * x); }
 
-// Table (entry 2a+b) from the four fp4 sums.
-__device__ __forceinline__ v4i table_f4(float s, float t, float u, float v) {
-  const int S = f4_count(s), T = f4_count(t), U = f4_count(u), V = f4_count(v);
+// Table (entry 2a+b) from the four sums of the X and P planes
+// (planes16_f4x), with this call's counts (n(0), n(1), m, .) of i and j and
+// the K fields the loop covered.
+__device__ __forceinline__ v4i table_f4x(float xx, float xy, float yx, float yy, const v4i& ci,
+                                         const v4i& cj, int kpad) {
+  const int XX = f4_count(xx), XY = f4_count(xy), YX = f4_count(yx), YY = f4_count(yy);
+  const int S = XX + XY + YX + YY - ci.y - cj.y - kpad;
+  const int T = XY + YY - cj.z, U = YX + YY - ci.z, V = YY;
   return v4i{4 * V - 2 * T - 2 * U + S, 2 * U - S, 2 * T - S, S};
 }
 
-// One 256-field super-step (16 bytes per lane and row) of the four sums:
-// two MFMA steps of 128 fields.
+// One 256-field super-step (16 bytes per lane and row) of the four sums of
+// the X and P planes (planes16_f4x): two MFMA steps of 128 fields.
 template <int WM, int WN>
 __device__ __forceinline__ void mma_superstep_f4(const u4 (&xa)[WM], const u4 (&xb)[WN],
                                                  v4f (&acc)[WM][WN][4]) {
@@ -216,16 +238,16 @@ __device__ __forceinline__ void mma_superstep_f4(const u4 (&xa)[WM], const u4 (&
 #pragma unroll
     for (int n = 0; n < WN; ++n) {
       unsigned r0[2], p0[2], r1[2], p1[2];
-      planes16_f4(word_of(xb[n], 2 * h), r0, p0);
-      planes16_f4(word_of(xb[n], 2 * h + 1), r1, p1);
+      planes16_f4x(word_of(xb[n], 2 * h), r0, p0);
+      planes16_f4x(word_of(xb[n], 2 * h + 1), r1, p1);
       b0[n] = operand_f4(r0, r1);
       b1[n] = operand_f4(p0, p1);
     }
 #pragma unroll
     for (int m = 0; m < WM; ++m) {
       unsigned r0[2], p0[2], r1[2], p1[2];
-      planes16_f4(word_of(xa[m], 2 * h), r0, p0);
-      planes16_f4(word_of(xa[m], 2 * h + 1), r1, p1);
+      planes16_f4x(word_of(xa[m], 2 * h), r0, p0);
+      planes16_f4x(word_of(xa[m], 2 * h + 1), r1, p1);
       const v8i a0 = operand_f4(r0, r1), a1 = operand_f4(p0, p1);
 #pragma unroll
       for (int n = 0; n < WN; ++n) {
@@ -478,23 +500,32 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     });
 
   // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
+  const int kpad = (int)((a.n_f + 255) / 256 * 256);  // fields the fp4 loop covers
 #pragma unroll
   for (int m = 0; m < WM; ++m) {
     double wi[4][2];
+    v4i ci[4];  // this call's counts of rows i (fp4 form)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) side_factors(a, 0, row0 + 16 * m + 4 * g + e, wi[e]);
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = row0 + 16 * m + 4 * g + e;
+      side_factors(a, 0, i, wi[e]);
+      if constexpr (F4) ci[e] = reinterpret_cast<const v4i*>(a.chunk_a)[i < a.n_a ? i : a.n_a - 1];
+    }
 #pragma unroll
     for (int n = 0; n < WN; ++n) {
       const int64_t j = col0 + 16 * n + rl;
       double wj[2];
       side_factors(a, 1, j, wj);
+      v4i cj{0, 0, 0, 0};
+      if constexpr (F4) cj = reinterpret_cast<const v4i*>(a.chunk_b)[j < a.n_b ? j : a.n_b - 1];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i = row0 + 16 * m + 4 * g + e;
         const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
         v4i t;
         if constexpr (F4)
-          t = table_f4(acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]);
+          t = table_f4x(acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e],
+                        ci[e], cj, kpad);
         else
           t = v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]};
         emit_pair(a, valid, i, j, t, wi[e], wj);
