@@ -160,7 +160,8 @@ int ccc_3way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* ta
  * same tables, counts and CCC as one call over all fields.  CCC_ERR_RANGE if
  * 4*n_f > INT32_MAX for this chunk; keeping the accumulated total within
  * range is the caller's duty (the counts' m_i bound it).  n_a or n_b == 0 is
- * valid and writes nothing.
+ * valid and writes nothing.  A CCC_ACCUMULATE call uses (n_a + n_b) * 16 bytes
+ * of the library workspace for its chunk's own counts.
  */
 int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* vb, int64_t n_b,
                    int64_t ldb, int64_t n_f, int32_t* tables, int32_t* counts_a,

@@ -237,7 +237,8 @@ __device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j,
 #pragma unroll
         for (int x = 0; x < 8; ++x) S[x] = tile2::f4_count(acc[m][c][x][e]);
         table3_f4(S, t);
-        emit_triple(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c]);
+        // the wave's stage buffers are free now: stage the stores there
+        emit_triple_staged(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c], &stage[0][0][0]);
       }
     }
 }
@@ -512,6 +513,10 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
   for (int c = 0; c < 4; ++c) {
     xyz[c] = part[0][4 * wave + c][lane] + part[1][4 * wave + c][lane] +
              part[2][4 * wave + c][lane] + part[3][4 * wave + c][lane];
+  }
+  if constexpr (F4) __syncthreads();  // every wave's sums are read: part[wave] stages its stores
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
     const int64_t k = k0 + 16 * c + rl;
     const int64_t kk = k > j && k < n ? k : j;  // a valid row for invalid lanes
     triple_factors(a, kk, wk[c]);
@@ -544,7 +549,11 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
       t[2] = (int)(4u * Y - 2u * XY - 2u * YZ[c] + XYZ);
       t[1] = (int)(4u * Z[c] - 2u * XZ - 2u * YZ[c] + XYZ);
       t[0] = (int)(S8 - 4u * (X + Y + Z[c]) + 2u * (XY + XZ + YZ[c]) - XYZ);
-      emit_triple(a, valid, i, j, k, t, wi, wj, wk[c]);
+      if constexpr (F4)
+        emit_triple_staged(a, valid, i, j, k, t, wi, wj, wk[c],
+                           reinterpret_cast<u4*>(&part[wave][0][0]));
+      else
+        emit_triple(a, valid, i, j, k, t, wi, wj, wk[c]);
     }
   }
 }

@@ -88,4 +88,61 @@ __device__ __forceinline__ void emit_triple(const Triple3Args& a, bool valid, in
   }
 }
 
+// emit_triple with the dense output written through LDS so that every store
+// instruction covers whole stretches of memory.  Every lane of the wave must
+// call it; lane (g, rl) holds triple (i, j, k) with k = k_base + rl for one i
+// per 16-lane group g (consecutive triples when valid, since T(i,j,k) grows by
+// one with k).  Each group writes its 16 tables (32 B each) and CCC rows
+// (64 B each) into `scratch` (wave-private, 384 x 16 B) in output order, then
+// lane rl stores 16-byte piece rl of each 256-byte stretch, skipping pieces of
+// invalid triples.  Selection mode falls back to emit_triple.
+__device__ __forceinline__ void emit_triple_staged(const Triple3Args& a, bool valid, int64_t i,
+                                                   int64_t j, int64_t k, const int (&t)[8],
+                                                   const double (&wi)[2], const double (&wj)[2],
+                                                   const double (&wk)[2], u4* scratch) {
+  if (a.sel.count) {
+    emit_triple(a, valid, i, j, k, t, wi, wj, wk);
+    return;
+  }
+  valid = valid && i >= a.i_begin && i < a.i_end;
+  const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+  const unsigned gm = (unsigned)(__ballot(valid ? 1 : 0) >> (16 * g)) & 0xFFFFu;
+  const int64_t p = valid ? triple_index(a.n, i, j, k) - a.t_base - rl : 0;
+  const int first = gm ? __ffs(gm) - 1 : 0;
+  const int64_t p0 = __shfl(p, 16 * g + first);  // entry of the group's lane 0 (may be unused)
+  u4* T = scratch + 32 * g;        // 16 tables of the group: 32 x 16 B
+  u4* C = scratch + 128 + 64 * g;  // 16 CCC rows: 64 x 16 B
+  if (a.tables) {
+    T[2 * rl] = u4{(unsigned)t[0], (unsigned)t[1], (unsigned)t[2], (unsigned)t[3]};
+    T[2 * rl + 1] = u4{(unsigned)t[4], (unsigned)t[5], (unsigned)t[6], (unsigned)t[7]};
+  }
+  if (a.ccc) {
+    double r[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (valid) triple_ccc(t, wi, wj, wk, r);
+    double2* Cd = reinterpret_cast<double2*>(C + 4 * rl);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) Cd[x] = double2{r[2 * x], r[2 * x + 1]};
+  }
+  // the wave's LDS accesses run in program order; keep the compiler to it
+  asm volatile("" ::: "memory");
+  if (a.tables) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int piece = 16 * q + rl;
+      const u4 d = T[piece];
+      if ((gm >> (piece >> 1)) & 1u)
+        reinterpret_cast<u4*>(a.tables + 8 * p0)[piece] = d;
+    }
+  }
+  if (a.ccc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int piece = 16 * q + rl;
+      const u4 d = C[piece];
+      if ((gm >> (piece >> 2)) & 1u) reinterpret_cast<u4*>(a.ccc + 8 * p0)[piece] = d;
+    }
+  }
+  asm volatile("" ::: "memory");  // the scratch is reused by the next call
+}
+
 }  // namespace ccc
