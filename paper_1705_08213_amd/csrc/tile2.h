@@ -47,6 +47,51 @@ __device__ __forceinline__ void emit_pair(const Pair2Args& a, bool valid, int64_
   store_pair(p - a.p_base, t, wi, wj, a.tables, a.ccc);
 }
 
+// emit_pair with the CCC rows written through LDS, so that each store
+// instruction covers 256 contiguous bytes.  Every lane of the wave must call
+// it; lane (g, rl) holds pair (i, j) with j = j_base + rl for one i per
+// 16-lane group g (consecutive entries when valid).  The group's 16 CCC rows
+// (32 B each) go into `scratch` (wave-private, 128 x 16 B) in output order,
+// then lane rl stores 16-byte piece rl of each 256-byte stretch.  Tables are
+// stored directly (16 lanes x 16 B are already contiguous).  Selection and
+// accumulating calls fall back to emit_pair.
+__device__ __forceinline__ void emit_pair_staged(const Pair2Args& a, bool valid, int64_t i,
+                                                 int64_t j, v4i t, const double (&wi)[2],
+                                                 const double (&wj)[2], u4* scratch) {
+  if (a.sel.count || a.accumulate) {
+    emit_pair(a, valid, i, j, t, wi, wj);
+    return;
+  }
+  valid = valid && i >= a.row_begin && i < a.row_end;
+  const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+  const int64_t p = valid ? (a.tri ? pair_index(a.n_a, i, j) : i * a.n_b + j) - a.p_base : 0;
+  // streaming stores: the dense output is written once and not read back here
+  if (valid && a.tables)
+    __builtin_nontemporal_store(t, reinterpret_cast<v4i*>(a.tables + 4 * p));
+  if (!a.ccc) return;
+  const unsigned gm = (unsigned)(__ballot(valid ? 1 : 0) >> (16 * g)) & 0xFFFFu;
+  const int first = gm ? __ffs(gm) - 1 : 0;
+  const int64_t p0 = __shfl(p - rl, 16 * g + first);  // entry of the group's lane 0
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  if (valid) pair_ccc(t, wi, wj, r);
+  u4* C = scratch + 32 * g;
+  double2* Cd = reinterpret_cast<double2*>(C + 2 * rl);
+  Cd[0] = double2{r[0], r[1]};
+  Cd[1] = double2{r[2], r[3]};
+  // the wave's LDS accesses run in program order; keep the compiler to it
+  asm volatile("" ::: "memory");
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int piece = 16 * q + rl;
+    const u4 d = C[piece];
+    if ((gm >> (piece >> 1)) & 1u)
+      __builtin_nontemporal_store(v4u{d.x, d.y, d.z, d.w},
+                                  reinterpret_cast<v4u*>(a.ccc + 4 * p0) + piece);
+  }
+  asm volatile("" ::: "memory");  // the scratch is reused by the next call
+}
+
 // Factors of row x of A (side 0) or B (side 1), clamped into range; only
 // computed when some CCC value is produced.
 __device__ __forceinline__ void side_factors(const Pair2Args& a, int side, int64_t x,
@@ -677,9 +722,11 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
         side_factors(a, 0, i, wi);
         const int c11 = own[r][n][e];
         const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
-        emit_pair(a, valid, i, j,
-                  v4i{nf4 - 2 * n1i - 2 * n1j + c11, 2 * n1j - c11, 2 * n1i - c11, c11}, wi,
-                  wj);
+        const v4i t{nf4 - 2 * n1i - 2 * n1j + c11, 2 * n1j - c11, 2 * n1i - c11, c11};
+        if constexpr (F4)  // `part` is free after the reduction: stage the CCC stores
+          emit_pair_staged(a, valid, i, j, t, wi, wj, reinterpret_cast<u4*>(&part[wave][0][0]));
+        else
+          emit_pair(a, valid, i, j, t, wi, wj);
       }
   }
 }
