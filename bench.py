@@ -187,7 +187,8 @@ def bench_2way(args, lib, n_v, n_f, missing, gen, path, workload, cpu_seconds):
                                traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                                algorithmic_bytes=n_v * ((n_f + 3) // 4) + 48 * P + 32 * n_v,
                                kernel="mfma2_kernel", kernel_ms=kms, operands=fmt,
-                               ops_per_comparison=2 if missing == 0.0 else 8)
+                               ops_per_comparison=2 if missing == 0.0 else 8,
+                               frac_of_int8_peak=ach / INT8_PEAK_TOPS)
         if args.select_threshold is not None:
             thr = args.select_threshold
             log(f"timing threshold selection at {thr}")
@@ -244,7 +245,8 @@ def bench_3way(args, lib, missing, workload):
                 frac=ach / peak, traffic=None,
                 traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                 algorithmic_bytes=alg_bytes, kernel="mfma3_kernel", kernel_ms=kms,
-                operands=fmt, ops_per_comparison=int(ops_per))
+                operands=fmt, ops_per_comparison=int(ops_per),
+                frac_of_int8_peak=ach / INT8_PEAK_TOPS)
     roof["traffic"] = committed_traffic(
         MFMA3_SOURCES, "profiles/mfma3_3way_n2048_f16384.md" if missing > 0.0
         else "profiles/mfma3_3way_complete_n2048_f16384.md")
@@ -322,7 +324,8 @@ def bench_multi(args, lib):
                              traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                              algorithmic_bytes=n_v * n_f + P * s * s * 12 + 32 * n_v,
                              kernel="multi2_kernel", kernel_ms=kms,
-                             ops_per_comparison=int(2 * s * s)))
+                             ops_per_comparison=int(2 * s * s),
+                             frac_of_int8_peak=ach / INT8_PEAK_TOPS))
     if not args.no_cpu:
         import oracle
         rows, pairs, dt = oracle_sample(lambda r0, r1: oracle.multi_two_way(v, n_f, s, r0, r1),
