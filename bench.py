@@ -107,9 +107,10 @@ def timed(fn, steps, warmup, lib, kernel):
 
 def oracle_sample(call, units, n_rows, chunk, seconds):
     """Runs call(r0, r1) over consecutive row chunks from row 0 until `seconds`
-    of CPU time have passed (or the rows run out); returns (rows, units, s)."""
+    of CPU time have passed (at least one chunk) or the rows run out; returns
+    (rows, units, s)."""
     rows, done, dt = 0, 0, 0.0
-    while rows < n_rows and dt < seconds:
+    while rows < n_rows and (rows == 0 or dt < seconds):
         r1 = min(n_rows, rows + chunk)
         t = time.perf_counter()
         call(rows, r1)
