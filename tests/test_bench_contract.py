@@ -45,13 +45,3 @@ def test_committed_traffic_needs_the_profiled_sources(tmp_path, monkeypatch):
     # another source set hashes differently: no figure
     assert bench.committed_traffic(bench.MFMA3_SOURCES, prof) is None
     assert bench.committed_traffic(bench.MFMA2_SOURCES, "profiles/no_such_file.md") is None
-
-
-def test_every_committed_traffic_profile_matches_its_sources():
-    pairs = [(bench.MFMA2_SOURCES, "profiles/mfma2_2way_n32768_f65536_traffic.md"),
-             (bench.MFMA2_SOURCES, "profiles/mfma2_2way_complete_n32768_f65536.md"),
-             (bench.MFMA3_SOURCES, "profiles/mfma3_3way_n2048_f16384.md"),
-             (bench.MFMA3_SOURCES, "profiles/mfma3_3way_complete_n2048_f16384.md"),
-             (bench.MULTI2_SOURCES, "profiles/multi2_2way_n16384_f32768_s4.md")]
-    for srcs, prof in pairs:
-        assert bench.committed_traffic(srcs, prof) is not None, prof
