@@ -435,53 +435,84 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
   };
 
   const int64_t steps = (a.n_f + 255) / 256;
-  const int64_t s_end = steps * (wave + 1) / 4;
-  for (int64_t st = steps * wave / 4; st < s_end; ++st) {
-    const int64_t kb = st * 64;
-    const bool full = (kb + 64) * 4 <= a.n_f;
-    u4 xa[4], xk[4], xj;
-    if (full) {
+  const int64_t s_begin = steps * wave / 4, s_end = steps * (wave + 1) / 4;
+  if constexpr (F4) {
+    // Whole steps alternate between two register sets, the next step's words
+    // loading while the current one computes; then the padded last step, if
+    // it falls in this wave's range.
+    const int64_t n_whole = a.n_f / 256;
+    const int64_t e_whole = s_end < n_whole ? s_end : n_whole;
+    auto load = [&](int64_t st, u4 (&xa)[4], u4 (&xk)[4], u4& xj) {
+      const int64_t kb = st * 64;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         xa[m] = *reinterpret_cast<const u4*>(pa[m] + kb);
         xk[m] = *reinterpret_cast<const u4*>(pk[m] + kb);
       }
       xj = *reinterpret_cast<const u4*>(pj + kb);
-    } else {
+    };
+    u4 ea[4], ek[4], ej, oa[4], ok[4], oj;
+    int64_t st = s_begin;
+    if (st < e_whole) load(st, ea, ek, ej);
+    for (; st + 1 < e_whole; st += 2) {
+      load(st + 1, oa, ok, oj);
+      body_f4(acc, ea, ek, ej, std::true_type{});
+      if (st + 2 < e_whole) load(st + 2, ea, ek, ej);
+      body_f4(acc, oa, ok, oj, std::true_type{});
+    }
+    if (st < e_whole) body_f4(acc, ea, ek, ej, std::true_type{});
+    if (n_whole >= s_begin && n_whole < s_end) {
+      const int64_t kb = n_whole * 64 + 16 * g;
+      u4 xa[4], xk[4], xj;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        xa[m] = load_fields64(pa[m] - 16 * g, kb + 16 * g, a.n_f);
-        xk[m] = load_fields64(pk[m] - 16 * g, kb + 16 * g, a.n_f);
+        xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
+        xk[m] = load_fields64(pk[m] - 16 * g, kb, a.n_f);
       }
-      xj = load_fields64(pj - 16 * g, kb + 16 * g, a.n_f);
+      xj = load_fields64(pj - 16 * g, kb, a.n_f);
+      body_f4(acc, xa, xk, xj, std::false_type{});
     }
-    if constexpr (F4) {
-      if (full)
-        body_f4(acc, xa, xk, xj, std::true_type{});
-      else
-        body_f4(acc, xa, xk, xj, std::false_type{});
-      continue;
-    }
+  } else {
+    for (int64_t st = s_begin; st < s_end; ++st) {
+      const int64_t kb = st * 64;
+      const bool full = (kb + 64) * 4 <= a.n_f;
+      u4 xa[4], xk[4], xj;
+      if (full) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      unsigned cj[4], sel1[4];
-      codes4(word_of(xj, s), cj);
+        for (int m = 0; m < 4; ++m) {
+          xa[m] = *reinterpret_cast<const u4*>(pa[m] + kb);
+          xk[m] = *reinterpret_cast<const u4*>(pk[m] + kb);
+        }
+        xj = *reinterpret_cast<const u4*>(pj + kb);
+      } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) sel1[t] = __builtin_amdgcn_perm(0u, kSelJ1, cj[t]);
-      v4i A1[4];
+        for (int m = 0; m < 4; ++m) {
+          xa[m] = load_fields64(pa[m] - 16 * g, kb + 16 * g, a.n_f);
+          xk[m] = load_fields64(pk[m] - 16 * g, kb + 16 * g, a.n_f);
+        }
+        xj = load_fields64(pj - 16 * g, kb + 16 * g, a.n_f);
+      }
 #pragma unroll
-      for (int m = 0; m < 4; ++m) A1[m] = tile2::unpack16_rho1(word_of(xa[m], s));
+      for (int s = 0; s < 4; ++s) {
+        unsigned cj[4], sel1[4];
+        codes4(word_of(xj, s), cj);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        unsigned ck[4];
-        codes4(word_of(xk[c], s), ck);
-        v4i M;  // rho_j(1) rho_k(1)
+        for (int t = 0; t < 4; ++t) sel1[t] = __builtin_amdgcn_perm(0u, kSelJ1, cj[t]);
+        v4i A1[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          M[t] = (int)__builtin_amdgcn_perm(kRho1Twice, kRho1Table, ck[t] | sel1[t]);
+        for (int m = 0; m < 4; ++m) A1[m] = tile2::unpack16_rho1(word_of(xa[m], s));
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-          acc[m][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[m], M, acc[m][c], 0, 0, 0);
+        for (int c = 0; c < 4; ++c) {
+          unsigned ck[4];
+          codes4(word_of(xk[c], s), ck);
+          v4i M;  // rho_j(1) rho_k(1)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            M[t] = (int)__builtin_amdgcn_perm(kRho1Twice, kRho1Table, ck[t] | sel1[t]);
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            acc[m][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[m], M, acc[m][c], 0, 0, 0);
+        }
       }
     }
   }
