@@ -113,14 +113,14 @@ __device__ __forceinline__ int next_item(unsigned* counter, int* slot) {
 
 template <int WM, int WN, bool F4>
 __device__ __forceinline__ void mfma_item(const Pair2Args& a, int64_t tiles_side, int tile,
-                                          u4 (*stage)[WM + WN][64]) {
+                                          u4 (*stage)[2 * WM + 2 * WN][64]) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   const int wave = threadIdx.x >> 6;
   int64_t sq_i, sq_j;
   tri_tile(tile >> 1, tiles_side, sq_i, sq_j);
   const int64_t I = sq_i, J = 2 * sq_j + (tile & 1);
   tile2::mfma2_wave_tile<WM, WN, F4>(a, I * BM + (wave & 1) * 16 * WM,
-                                     J * BN + (wave >> 1) * 16 * WN, stage + 2 * wave);
+                                     J * BN + (wave >> 1) * 16 * WN, stage);
 }
 
 // One persistent launch per tile variant present in the batch (each variant's
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256, 2) void many_mfma_kernel(const ProbDesc* __res
                                                            unsigned* __restrict__ counter,
                                                            double gamma) {
   __shared__ int slot;
-  __shared__ u4 stage[4 * 2][WM + WN][64];  // two fp4 stage buffers per wave
+  __shared__ u4 stage[2][2 * WM + 2 * WN][64];  // the workgroup's two fp4 stage buffers
   for (;;) {
     const int it = next_item(counter, &slot);
     if (it >= n_items) break;

@@ -25,17 +25,17 @@ __global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tile
     I = b / tiles_n;
     J = b % tiles_n;
   }
-  // 64 KB: the complete-data form's partial tiles, or else each wave's two
-  // fp4 stage buffers of WM + WN rows
+  // 64 KB: the complete-data form's partial tiles, or else the workgroup's
+  // two fp4 stage buffers of 2 WM + 2 WN row blocks
   __shared__ v4i part[4][16][64];
-  static_assert(sizeof(part) >= 4 * 2 * (WM + WN) * 64 * sizeof(u4), "stage buffers fit");
+  static_assert(sizeof(part) >= 2 * (2 * WM + 2 * WN) * 64 * sizeof(u4), "stage buffers fit");
   if (tile2::workgroup_complete<WM, WN>(a, I * BM, J * BN)) {
     tile2::mfma2_coop_complete<WM, WN, F4>(a, I * BM, J * BN, part);
     return;
   }
-  u4(*stage)[WM + WN][64] = reinterpret_cast<u4(*)[WM + WN][64]>(&part[0][0][0]) + 2 * wave;
-  tile2::mfma2_wave_tile<WM, WN, F4>(a, I * BM + (wave & 1) * 16 * WM,
-                                     J * BN + (wave >> 1) * 16 * WN, stage);
+  tile2::mfma2_wave_tile<WM, WN, F4>(
+      a, I * BM + (wave & 1) * 16 * WM, J * BN + (wave >> 1) * 16 * WN,
+      reinterpret_cast<u4(*)[2 * WM + 2 * WN][64]>(&part[0][0][0]));
 }
 
 template <int WM, int WN>

@@ -125,12 +125,13 @@ __device__ __forceinline__ void table3_f4(const int (&S)[8], int (&t)[8]) {
   }
 }
 
+// fp4 body of general_wave (see there).
 __device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j, int64_t row0,
-                                                int64_t col0, const uint8_t* const (&pa)[WI],
+                                                int64_t col0, bool active,
+                                                const uint8_t* const (&pa)[WI],
                                                 const uint8_t* const (&pk)[WK],
-                                                const uint8_t* pj,
-                                                u4 (*stage)[WI + WK + 1][64]) {
-  const int lane = threadIdx.x & 63;
+                                                const uint8_t* pj, u4* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, rl = lane & 15;
   const int64_t n = a.n;
   v4f acc[WI][WK][8];
@@ -186,29 +187,45 @@ __device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j,
     }
   };
 
-  // Whole super-steps through the LDS stage (stage rows: k rows, i rows, j),
-  // then the masked tail from plain loads.
+  // Whole super-steps through the workgroup's LDS stage: the unit's 2 WI
+  // i blocks, 2 WK k blocks and the j row (16 rows x 64 bytes per block, the
+  // j block 16 copies of one row), three blocks copied per wave, one barrier
+  // per step (every block has landed; the buffer read one step earlier is
+  // free).  Inactive waves only copy.  Then the masked tail from plain loads.
+  constexpr int NB = 2 * WI + 2 * WK + 1, BPW = (NB + 3) / 4;
+  auto stage = reinterpret_cast<u4(*)[NB][64]>(lds);
+  const int64_t I0 = row0 - (wave & 1) * 16 * WI, K0 = col0 - (wave >> 1) * 16 * WK;
+  const uint8_t* src[BPW];
+#pragma unroll
+  for (int t = 0; t < BPW; ++t) {
+    const int b = BPW * wave + t;
+    int64_t r = b < 2 * WI ? I0 + 16 * b + rl : (b < NB - 1 ? K0 + 16 * (b - 2 * WI) + rl : j);
+    src[t] = a.v + (r < n ? r : n - 1) * a.ld + 16 * g;
+  }
   const int64_t nfull = a.n_f / 256;
   auto issue = [&](int64_t st, int buf) {
 #pragma unroll
-    for (int c = 0; c < WK; ++c) tile2::stage_row(pk[c] + st * 64, &stage[buf][c][0]);
-#pragma unroll
-    for (int m = 0; m < WI; ++m) tile2::stage_row(pa[m] + st * 64, &stage[buf][WK + m][0]);
-    tile2::stage_row(pj + st * 64, &stage[buf][WK + WI][0]);
+    for (int t = 0; t < BPW; ++t)
+      if (BPW * wave + t < NB) tile2::stage_row(src[t] + st * 64, &stage[buf][BPW * wave + t][0]);
   };
+  const int ia = (wave & 1) * WI, kb = 2 * WI + (wave >> 1) * WK;
   if (nfull > 0) issue(0, 0);
   for (int64_t st = 0; st < nfull; ++st) {
     const int buf = (int)(st & 1);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's rows are in LDS
-    u4 xa[WI], xk[WK];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's blocks have landed
+    __syncthreads();                                   // every wave's have; buf ^ 1 is free
+    u4 xa[WI], xk[WK], xj;  // read before the next copy is issued
+    if (active) {
 #pragma unroll
-    for (int c = 0; c < WK; ++c) xk[c] = stage[buf][c][lane];
+      for (int c = 0; c < WK; ++c) xk[c] = stage[buf][kb + c][lane];
 #pragma unroll
-    for (int m = 0; m < WI; ++m) xa[m] = stage[buf][WK + m][lane];
-    const u4 xj = stage[buf][WK + WI][lane];
+      for (int m = 0; m < WI; ++m) xa[m] = stage[buf][ia + m][lane];
+      xj = stage[buf][NB - 1][lane];
+    }
     if (st + 1 < nfull) issue(st + 1, buf ^ 1);
-    body(xa, xk, xj);
+    if (active) body(xa, xk, xj);
   }
+  if (!active) return;
   if (nfull * 256 < a.n_f) {
     const int64_t kb = nfull * 64 + 16 * g;
     u4 xa[WI], xk[WK];
@@ -237,19 +254,23 @@ __device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j,
 #pragma unroll
         for (int x = 0; x < 8; ++x) S[x] = tile2::f4_count(acc[m][c][x][e]);
         table3_f4(S, t);
-        // the wave's stage buffers are free now: stage the stores there
-        emit_triple_staged(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c], &stage[0][0][0]);
+        // stage the stores past the workgroup's stage buffers (other waves may
+        // still read those): 384 x 16 bytes per wave
+        emit_triple_staged(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c],
+                           lds + 2 * NB * 64 + 384 * wave);
       }
     }
 }
 
 // General unit, one wave: the (16 WI) x (16 WK) tile of (i, k) at rows row0..,
-// columns col0.. for middle vector j, eight MFMA planes.  fp4 form: the rows
-// of the next super-step travel into this wave's LDS stage (two buffers of
-// WK + WI + 1 rows) while the current one is multiplied.
+// columns col0.. for middle vector j, eight MFMA planes.  `active`: the tile
+// holds a triple i < j < k.  int8 form: inactive waves return at once.  fp4
+// form: every wave of the workgroup calls it; the unit's rows of the next
+// super-step travel into the workgroup's LDS stage (`lds`) while the current
+// one is multiplied, and inactive waves only take part in the copies.
 template <bool F4>
 __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, int64_t row0,
-                                             int64_t col0, u4 (*stage)[WI + WK + 1][64]) {
+                                             int64_t col0, bool active, u4* lds) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
   const int64_t n = a.n;
@@ -269,9 +290,10 @@ __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, in
   const uint8_t* pj = a.v + j * a.ld + 16 * g;
 
   if constexpr (F4) {
-    general_wave_f4(a, j, row0, col0, pa, pk, pj, stage);
+    general_wave_f4(a, j, row0, col0, active, pa, pk, pj, lds);
     return;
   }
+  if (!active) return;
 
   v4i acc[WI][WK][8];
 #pragma unroll
@@ -593,10 +615,12 @@ template <bool F4>
 __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid ug,
                                                        const int64_t* __restrict__ offs,
                                                        int64_t unit_base, int64_t count) {
-  // 64 KB: the complete-data partial tiles, or else each wave's two fp4 stage
-  // buffers of WK + WI + 1 rows
+  // 64 KB: the complete-data partial tiles, or else the workgroup's two fp4
+  // stage buffers of 2 WI + 2 WK + 1 row blocks and each wave's 6 KB of
+  // store staging
   __shared__ v4i part[4][16][64];
-  static_assert(sizeof(part) >= 4 * 2 * (WI + WK + 1) * 64 * sizeof(u4), "stage buffers fit");
+  static_assert(sizeof(part) >= (2 * (2 * WI + 2 * WK + 1) * 64 + 4 * 384) * sizeof(u4),
+                "stage buffers fit");
   const int wave = threadIdx.x >> 6;
   const int64_t n = a.n;
   const int64_t u = unit_base + xcd_unit(blockIdx.x, count);
@@ -618,9 +642,9 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid u
 
   const int64_t row0 = it * BI + (wave & 1) * 16 * WI;  // i range of this wave
   const int64_t col0 = kt * BK + (wave >> 1) * 16 * WK; // k range of this wave
-  if (row0 >= j || col0 + 16 * WK - 1 <= j || col0 >= n) return;
-  general_wave<F4>(a, j, row0, col0,
-                   reinterpret_cast<u4(*)[WI + WK + 1][64]>(&part[0][0][0]) + 2 * wave);
+  const bool active = !(row0 >= j || col0 + 16 * WK - 1 <= j || col0 >= n);
+  if (!F4 && !active) return;
+  general_wave<F4>(a, j, row0, col0, active, reinterpret_cast<u4*>(&part[0][0][0]));
 }
 
 // G[r][c] = sum_q rho_{g0+r,q}(1) rho_{g0+c,q}(1) for r, c < ng: the pair

@@ -197,9 +197,9 @@ __device__ __forceinline__ void mma_superstep_rho1(const u4 (&pa)[WM], const u4 
 // four sums S = sum rho_i rho_j, T = sum rho_i P_j, U = sum P_i rho_j,
 // V = sum P_i P_j give the table:
 //   C11 = S,  C10 = 2T - S,  C01 = 2U - S,  C00 = 4V - 2T - 2U + S
-// (rho(0) = 2P - rho(1)); the general loop reaches them through the cheaper
-// plane X = rho(1) + missing (planes16_f4x).  Fields past n_f carry the missing code, which is
-// zero in both planes.
+// (rho(0) = 2P - rho(1)); the general 2-way loop reaches them through the
+// cheaper plane U = rho(1) + 2 [missing] (planes16_f4u).  Fields past n_f
+// carry the missing code, which is zero in rho(1) and P.
 // ---------------------------------------------------------------------------
 
 constexpr unsigned kEven2 = 0x55555555u;  // bit 0 of every 2-bit field
@@ -219,20 +219,27 @@ __device__ __forceinline__ void planes16_f4(unsigned w, unsigned (&r)[2], unsign
   p[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
 }
 
-// The 2-way planes X = lo + hi (= code - hi: rho(1), plus 1 on a missing or
-// padding field) and P, in nine operations.  rho(1) = X + P - 1, so with
-// K the fields a loop covers (padding included) and n(1), m this call's
-// counts, the sums XX, XY, YX, YY of X and P give
-//   S = XX + XY + YX + YY - n_i(1) - n_j(1) - K,   T = XY + YY - m_j,
-//   U = YX + YY - m_i,   V = YY
-// (sum_q X_i = n_i(1) + K - m_i and sum_q P_i = m_i over the K fields).
-__device__ __forceinline__ void planes16_f4x(unsigned w, unsigned (&r)[2], unsigned (&p)[2]) {
-  const unsigned s = w >> 1;
-  const unsigned x = w - (s & kEven2);
-  r[0] = x & kNib2;
-  r[1] = (x >> 2) & kNib2;
-  p[0] = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
-  p[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
+// The 2-way planes U = rho(1) + 2 [missing] (codes 00, 01, 10, 11 -> 0, 1,
+// 2, 2) and P of 16 fields as fp4 nibbles, in seven operations: even fields
+// in the low two bits of a nibble (e2m1 value = plane / 2), odd fields in
+// its middle two bits (value = plane; U = 2 is the pattern 0100, never 0110).
+// With s = w >> 1, h = s & kEven2 (hi at bit 0 of each field, 0 at bit 1)
+// and q = h >> 1, truth tables 0x20 = c & a & ~b and 0xA2 = c & (a | ~b):
+//   ue: bit 0 = lo & ~hi, bit 1 = hi         uo: the same at bits 1, 2
+//   pe: bit 0 = lo | ~hi                     po: the same at bit 1
+__device__ __forceinline__ void planes16_f4u(unsigned w, unsigned& ue, unsigned& uo, unsigned& pe,
+                                             unsigned& po) {
+  const unsigned s = w >> 1, h = s & kEven2, q = h >> 1;
+  ue = __builtin_amdgcn_bitop3_b32(w, h, 0x33333333u, 0x20);
+  uo = __builtin_amdgcn_bitop3_b32(s, q, 0x66666666u, 0x20);
+  pe = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
+  po = __builtin_amdgcn_bitop3_b32(s, q, 0x22222222u, 0xA2);
+}
+
+// fp4 MFMA with both E8M0 scales 2^(e - 127).
+template <int e>
+__device__ __forceinline__ v4f mfma_f4s(const v8i& a, const v8i& b, v4f c) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 4, 4, 0, e, 0, e);
 }
 
 // rho(1) of 16 fields; `complete` words hold no missing code, where
@@ -261,46 +268,59 @@ __device__ __forceinline__ v4f mfma_f4(const v8i& a, const v8i& b, v4f c) {
 
 __device__ __forceinline__ int f4_count(float x) { return (int)(4.0f * x); }
 
-// Table (entry 2a+b) from the four sums of the X and P planes
-// (planes16_f4x), with this call's counts (n(0), n(1), m, .) of i and j and
-// the K fields the loop covered.
-__device__ __forceinline__ v4i table_f4x(float xx, float xy, float yx, float yy, const v4i& ci,
+// Table (entry 2a+b) from the four sums of the U and P planes
+// (planes16_f4u) over the K fields of the loop: rho(1) = U + 2P - 2 gives
+//   S = UU + 2UP + 2PU + 4PP - 2 n_i(1) - 2 n_j(1) - 4K,
+//   T = UP + 2PP - 2 m_j,  U' = PU + 2PP - 2 m_i,  V = PP
+// (sum_q U_i = n_i(1) + 2 (K - m_i), sum_q P_i = m_i).
+__device__ __forceinline__ v4i table_f4u(float uu, float up, float pu, float pp, const v4i& ci,
                                          const v4i& cj, int kpad) {
-  const int XX = f4_count(xx), XY = f4_count(xy), YX = f4_count(yx), YY = f4_count(yy);
-  const int S = XX + XY + YX + YY - ci.y - cj.y - kpad;
-  const int T = XY + YY - cj.z, U = YX + YY - ci.z, V = YY;
+  const int UU = f4_count(uu), UP = f4_count(up), PU = f4_count(pu), PP = f4_count(pp);
+  const int S = UU + 2 * UP + 2 * PU + 4 * PP - 2 * ci.y - 2 * cj.y - 4 * kpad;
+  const int T = UP + 2 * PP - 2 * cj.z, U = PU + 2 * PP - 2 * ci.z, V = PP;
   return v4i{4 * V - 2 * T - 2 * U + S, 2 * U - S, 2 * T - S, S};
 }
 
-// One 256-field super-step (16 bytes per lane and row) of the four sums of
-// the X and P planes (planes16_f4x): two MFMA steps of 128 fields.
+// One 256-field super-step of the four sums of the U and P planes
+// (planes16_f4u): the MFMA step of the even fields of the lane's four words,
+// then the one of the odd fields, whose nibble values are twice as large
+// (scales 2^-1 on A and B).
 template <int WM, int WN>
-__device__ __forceinline__ void mma_superstep_f4(const u4 (&xa)[WM], const u4 (&xb)[WN],
-                                                 v4f (&acc)[WM][WN][4]) {
+__device__ __forceinline__ void mma_superstep_f4u(const u4 (&xa)[WM], const u4 (&xb)[WN],
+                                                  v4f (&acc)[WM][WN][4]) {
+  v8i bu[2][WN], bp[2][WN];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    v8i b0[WN], b1[WN];  // rho(1) and P planes
+  for (int n = 0; n < WN; ++n) {
+    unsigned ue[4], uo[4], pe[4], po[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) planes16_f4u(word_of(xb[n], q), ue[q], uo[q], pe[q], po[q]);
+    bu[0][n] = v8i{(int)ue[0], (int)ue[1], (int)ue[2], (int)ue[3], 0, 0, 0, 0};
+    bu[1][n] = v8i{(int)uo[0], (int)uo[1], (int)uo[2], (int)uo[3], 0, 0, 0, 0};
+    bp[0][n] = v8i{(int)pe[0], (int)pe[1], (int)pe[2], (int)pe[3], 0, 0, 0, 0};
+    bp[1][n] = v8i{(int)po[0], (int)po[1], (int)po[2], (int)po[3], 0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int m = 0; m < WM; ++m) {
+    unsigned ue[4], uo[4], pe[4], po[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) planes16_f4u(word_of(xa[m], q), ue[q], uo[q], pe[q], po[q]);
+    const v8i au0{(int)ue[0], (int)ue[1], (int)ue[2], (int)ue[3], 0, 0, 0, 0};
+    const v8i ap0{(int)pe[0], (int)pe[1], (int)pe[2], (int)pe[3], 0, 0, 0, 0};
+    const v8i au1{(int)uo[0], (int)uo[1], (int)uo[2], (int)uo[3], 0, 0, 0, 0};
+    const v8i ap1{(int)po[0], (int)po[1], (int)po[2], (int)po[3], 0, 0, 0, 0};
 #pragma unroll
     for (int n = 0; n < WN; ++n) {
-      unsigned r0[2], p0[2], r1[2], p1[2];
-      planes16_f4x(word_of(xb[n], 2 * h), r0, p0);
-      planes16_f4x(word_of(xb[n], 2 * h + 1), r1, p1);
-      b0[n] = operand_f4(r0, r1);
-      b1[n] = operand_f4(p0, p1);
+      acc[m][n][0] = mfma_f4s<127>(au0, bu[0][n], acc[m][n][0]);
+      acc[m][n][1] = mfma_f4s<127>(au0, bp[0][n], acc[m][n][1]);
+      acc[m][n][2] = mfma_f4s<127>(ap0, bu[0][n], acc[m][n][2]);
+      acc[m][n][3] = mfma_f4s<127>(ap0, bp[0][n], acc[m][n][3]);
     }
 #pragma unroll
-    for (int m = 0; m < WM; ++m) {
-      unsigned r0[2], p0[2], r1[2], p1[2];
-      planes16_f4x(word_of(xa[m], 2 * h), r0, p0);
-      planes16_f4x(word_of(xa[m], 2 * h + 1), r1, p1);
-      const v8i a0 = operand_f4(r0, r1), a1 = operand_f4(p0, p1);
-#pragma unroll
-      for (int n = 0; n < WN; ++n) {
-        acc[m][n][0] = mfma_f4(a0, b0[n], acc[m][n][0]);
-        acc[m][n][1] = mfma_f4(a0, b1[n], acc[m][n][1]);
-        acc[m][n][2] = mfma_f4(a1, b0[n], acc[m][n][2]);
-        acc[m][n][3] = mfma_f4(a1, b1[n], acc[m][n][3]);
-      }
+    for (int n = 0; n < WN; ++n) {
+      acc[m][n][0] = mfma_f4s<126>(au1, bu[1][n], acc[m][n][0]);
+      acc[m][n][1] = mfma_f4s<126>(au1, bp[1][n], acc[m][n][1]);
+      acc[m][n][2] = mfma_f4s<126>(ap1, bu[1][n], acc[m][n][2]);
+      acc[m][n][3] = mfma_f4s<126>(ap1, bp[1][n], acc[m][n][3]);
     }
   }
 }
@@ -311,45 +331,66 @@ __device__ __forceinline__ void stage_row(const uint8_t* src, u4* dst) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
 }
 
-// The super-step loop of a wave tile for the fp4 form.  The next
-// super-step's rows travel from memory straight into this wave's LDS stage
-// (two buffers of WN + WM rows x 64 lanes x 16 bytes) while the current one
-// is unpacked and multiplied, so no registers hold them in flight; each step
-// starts by waiting for its buffer and reading it into registers.  Then one
-// masked tail step from plain loads.  Row pointers include the lane's 16g
-// byte offset.
+// The fp4 super-step loop of a workgroup of four waves: 2 x 2 wave tiles of
+// (16 WM) x (16 WN) pairs, the workgroup tile at (I0, J0).  The waves share
+// rows, so each step's 2 WM + 2 WN row blocks (16 rows x 64 bytes, one
+// `global_load_lds_dwordx4` each: lane l's 16 bytes land at 16 l) travel
+// into the workgroup's LDS stage once, split over the waves, while the
+// previous step is unpacked and multiplied.  One barrier per step says that
+// every block of the step has landed and that the buffer read one step
+// earlier is free.  Every wave of the workgroup must call it; inactive
+// waves only copy their blocks.  Then the masked tail step of the active
+// waves from plain loads (pa, pb: this wave's rows, with the lane's 16g
+// byte offset).
 template <int WM, int WN, typename Step>
-__device__ __forceinline__ void wave_loop_f4(const uint8_t* const (&pa)[WM],
-                                             const uint8_t* const (&pb)[WN], int g, int64_t n_f,
-                                             u4 (*stage)[WM + WN][64], Step step) {
-  const int64_t nfull = n_f / 256;
-  const int64_t nbytes = (n_f + 3) / 4;
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void wg_loop_f4(const Pair2Args& a, int64_t I0, int64_t J0,
+                                           bool active, const uint8_t* const (&pa)[WM],
+                                           const uint8_t* const (&pb)[WN],
+                                           u4 (*stage)[2 * WM + 2 * WN][64], Step step) {
+  constexpr int NB = 2 * WM + 2 * WN, BPW = (NB + 3) / 4;  // blocks, blocks per wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, rl = lane & 15;
+  const uint8_t* src[BPW];
+#pragma unroll
+  for (int t = 0; t < BPW; ++t) {
+    const int b = BPW * wave + t;  // blocks 0 .. 2 WM - 1 are rows i, then rows j
+    int64_t r = b < 2 * WM ? I0 + 16 * b + rl : J0 + 16 * (b - 2 * WM) + rl;
+    if (b < 2 * WM)
+      src[t] = a.va + (r < a.n_a ? r : a.n_a - 1) * a.lda + 16 * g;
+    else
+      src[t] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
+  }
   auto issue = [&](int64_t s, int buf) {
 #pragma unroll
-    for (int n = 0; n < WN; ++n) stage_row(pb[n] + s * 64, &stage[buf][n][0]);
-#pragma unroll
-    for (int m = 0; m < WM; ++m) stage_row(pa[m] + s * 64, &stage[buf][WN + m][0]);
+    for (int t = 0; t < BPW; ++t)
+      if (BPW * wave + t < NB) stage_row(src[t] + s * 64, &stage[buf][BPW * wave + t][0]);
   };
+  const int ma = (wave & 1) * WM, nb = 2 * WM + (wave >> 1) * WN;
+  const int64_t nfull = a.n_f / 256, nbytes = (a.n_f + 3) / 4;
   if (nfull > 0) issue(0, 0);
   for (int64_t s = 0; s < nfull; ++s) {
     const int buf = (int)(s & 1);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this step's rows are in LDS
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's blocks have landed
+    __syncthreads();                                   // every wave's have; buf ^ 1 is free
+    // read before the next copy is issued (the compiler would otherwise wait
+    // for that copy before the reads)
     u4 xa[WM], xb[WN];
+    if (active) {
 #pragma unroll
-    for (int n = 0; n < WN; ++n) xb[n] = stage[buf][n][lane];
+      for (int n = 0; n < WN; ++n) xb[n] = stage[buf][nb + n][lane];
 #pragma unroll
-    for (int m = 0; m < WM; ++m) xa[m] = stage[buf][WN + m][lane];
+      for (int m = 0; m < WM; ++m) xa[m] = stage[buf][ma + m][lane];
+    }
     if (s + 1 < nfull) issue(s + 1, buf ^ 1);
-    step(xa, xb);
+    if (active) step(xa, xb);
   }
   const int64_t kt = nfull * 64;
-  if (kt < nbytes) {
+  if (active && kt < nbytes) {
     u4 xa[WM], xb[WN];
 #pragma unroll
-    for (int m = 0; m < WM; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kt + 16 * g, n_f);
+    for (int m = 0; m < WM; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kt + 16 * g, a.n_f);
 #pragma unroll
-    for (int n = 0; n < WN; ++n) xb[n] = load_fields64(pb[n] - 16 * g, kt + 16 * g, n_f);
+    for (int n = 0; n < WN; ++n) xb[n] = load_fields64(pb[n] - 16 * g, kt + 16 * g, a.n_f);
     step(xa, xb);
   }
 }
@@ -437,16 +478,22 @@ __device__ __forceinline__ void mma_superstep(const u4 (&pa)[WM], const u4 (&pb)
 }
 
 // One wave's (16 WM) x (16 WN) tile of pairs with first row row0 and first
-// column col0 (see the design notes above).  Waves whose tile holds no pair
-// to compute return at once; no barrier is used, so callers may skip waves.
-// `stage`: this wave's two LDS buffers of WM + WN rows (fp4 form only).
+// column col0 (see the design notes above); wave w of the workgroup holds
+// the tile at (I0 + (w & 1) 16 WM, J0 + (w >> 1) 16 WN).  int8 form: waves
+// whose tile holds no pair to compute return at once and no barrier is
+// used.  fp4 form: every wave of the workgroup must call it (the rows are
+// staged for the workgroup, `stage`: two buffers of 2 WM + 2 WN row blocks
+// of 1 KB); such waves only take part in the copies.
 template <int WM, int WN, bool F4>
 __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0, int64_t col0,
-                                                u4 (*stage)[WM + WN][64]) {
+                                                u4 (*stage)[2 * WM + 2 * WN][64]) {
   const int lane = threadIdx.x & 63;
-  if (row0 >= a.n_a || col0 >= a.n_b) return;
-  if (a.tri && row0 >= col0 + 16 * WN - 1) return;  // no pair i < j in this wave tile
+  // no pair i < j in this wave tile
+  const bool active = row0 < a.n_a && col0 < a.n_b && !(a.tri && row0 >= col0 + 16 * WN - 1);
+  if (!F4 && !active) return;
   const int g = lane >> 4, rl = lane & 15;
+  const int wave = threadIdx.x >> 6;
+  const int64_t I0 = row0 - (wave & 1) * 16 * WM, J0 = col0 - (wave >> 1) * 16 * WN;
   const uint8_t* pa[WM];
   const uint8_t* pb[WN];
 #pragma unroll
@@ -466,7 +513,7 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
   //   C10 = 2 n_i(1) - C11,  C01 = 2 n_j(1) - C11,
   //   C00 = 4 n_f - 2 n_i(1) - 2 n_j(1) + C11,
   // one MFMA plane instead of four.  The vote is wave-uniform.
-  bool mine = !a.accumulate && a.n_f > 0;
+  bool mine = active && !a.accumulate && a.n_f > 0;
 #pragma unroll
   for (int m = 0; m < WM; ++m) {
     int64_t r = row0 + 16 * m + rl;
@@ -486,12 +533,15 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     for (int m = 0; m < WM; ++m)
 #pragma unroll
       for (int n = 0; n < WN; ++n) acc1[m][n] = Acc{0, 0, 0, 0};
-    wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
-      if constexpr (F4)
-        mma_superstep_rho1_f4<WM, WN, false>(ca, cb, acc1);
-      else
+    if constexpr (F4)
+      wg_loop_f4<WM, WN>(a, I0, J0, true, pa, pb, stage,
+                         [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
+                           mma_superstep_rho1_f4<WM, WN, false>(ca, cb, acc1);
+                         });
+    else
+      wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
         mma_superstep_rho1<WM, WN>(ca, cb, acc1);
-    });
+      });
     const int nf4 = (int)(4 * a.n_f);
     double wj[WN][2];
     int n1j[WN];
@@ -535,10 +585,11 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[m][n][e] = Acc{0, 0, 0, 0};
   if constexpr (F4) {
-    wave_loop_f4<WM, WN>(pa, pb, g, a.n_f, stage,
-                         [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
-                           mma_superstep_f4<WM, WN>(xa, xb, acc);
-                         });
+    wg_loop_f4<WM, WN>(a, I0, J0, active, pa, pb, stage,
+                       [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
+                         mma_superstep_f4u<WM, WN>(xa, xb, acc);
+                       });
+    if (!active) return;
   } else
     wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
       mma_superstep<WM, WN>(ca, cb, acc);
@@ -569,7 +620,7 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
         const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
         v4i t;
         if constexpr (F4)
-          t = table_f4x(acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e],
+          t = table_f4u(acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e],
                         ci[e], cj, kpad);
         else
           t = v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]};

@@ -38,10 +38,16 @@ def test_operand_format_and_peak_follow_the_library():
     assert (fmt, peak, dt) == ("int8", bench.INT8_PEAK_TOPS, "i8")
 
 
-def test_committed_traffic_needs_the_profiled_sources(tmp_path, monkeypatch):
-    prof = "profiles/mfma2_2way_n32768_f65536_traffic.md"
-    t = bench.committed_traffic(bench.MFMA2_SOURCES, prof)
-    assert isinstance(t, int) and t > 26e9  # at least the output it writes
-    # another source set hashes differently: no figure
-    assert bench.committed_traffic(bench.MFMA3_SOURCES, prof) is None
-    assert bench.committed_traffic(bench.MFMA2_SOURCES, "profiles/no_such_file.md") is None
+def test_committed_traffic_needs_the_profiled_sources(tmp_path):
+    # a summary written for the current sources gives its figure; one for any
+    # other source set (or stale, or absent) gives none
+    import hashlib
+    h = hashlib.sha256(b"".join(open(os.path.join(bench.ROOT, f), "rb").read()
+                                for f in bench.MFMA2_SOURCES)).hexdigest()[:16]
+    prof = tmp_path / "summary.md"
+    prof.write_text(f"traffic_bytes_per_launch: 123456789\nkernel_source_sha256_16: {h}\n")
+    assert bench.committed_traffic(bench.MFMA2_SOURCES, str(prof)) == 123456789
+    assert bench.committed_traffic(bench.MFMA3_SOURCES, str(prof)) is None
+    prof.write_text("traffic_bytes_per_launch: 123456789\nkernel_source_sha256_16: 0123456789abcdef\n")
+    assert bench.committed_traffic(bench.MFMA2_SOURCES, str(prof)) is None
+    assert bench.committed_traffic(bench.MFMA2_SOURCES, str(tmp_path / "absent.md")) is None
