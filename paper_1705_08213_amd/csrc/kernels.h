@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace ccc {
@@ -135,6 +136,45 @@ __host__ __device__ __forceinline__ void unit_coords(int64_t u, const UnitGrid& 
 __host__ __device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t count) {
   const int64_t q = count >> 3, r = count & 7, x = b & 7;
   return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Strip order of the squares of a 2-way triangle launch, so that the
+// consecutive squares an XCD has in flight (xcd_unit hands each XCD a
+// contiguous run) share both their row and their column blocks: strips of
+// kStripRows square rows, walked column by column, rows ascending within a
+// column.  (A rectangle keeps the row-major order, which measured faster.)
+constexpr int64_t kStripRows = 8;
+
+// Triangle: square t of the squares (I, J), s0 <= I < s1, I <= J < T.  A
+// strip of h rows r0 .. r1 - 1 holds h (h - 1) / 2 squares in its first
+// h - 1 columns (column r0 + c has c + 1) and h in each of the T - r1 + 1
+// columns after them; the strips before the last are full, so the squares
+// before strip k number k A - H^2 k (k + 1) / 2 with
+// A = H (H - 1) / 2 + H (T - s0 + 1), H = kStripRows.
+__host__ __device__ inline void strip_square(int64_t t, int64_t T, int64_t s0, int64_t s1,
+                                             int64_t& I, int64_t& J) {
+  const int64_t H = kStripRows, nstrips = (s1 - s0 + H - 1) / H;
+  const int64_t A = H * (H - 1) / 2 + H * (T - s0 + 1);
+  auto before = [&](int64_t k) { return k * A - H * H * k * (k + 1) / 2; };
+  const double bq = (double)A - 0.5 * (double)(H * H);
+  const double disc = bq * bq - 2.0 * (double)(H * H) * (double)t;
+  int64_t k = (int64_t)((bq - sqrt(disc > 0.0 ? disc : 0.0)) / (double)(H * H));
+  if (k < 0) k = 0;
+  if (k > nstrips - 1) k = nstrips - 1;
+  while (k > 0 && before(k) > t) --k;
+  while (k + 1 < nstrips && before(k + 1) <= t) ++k;
+  const int64_t r0 = s0 + k * H, r1 = r0 + H < s1 ? r0 + H : s1, h = r1 - r0;
+  const int64_t u = t - before(k), diag = h * (h - 1) / 2;
+  if (u < diag) {  // column r0 + c holds rows r0 .. r0 + c
+    int64_t c = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+    while (c > 0 && c * (c + 1) / 2 > u) --c;
+    while ((c + 1) * (c + 2) / 2 <= u) ++c;
+    J = r0 + c;
+    I = r0 + (u - c * (c + 1) / 2);
+  } else {
+    J = r1 - 1 + (u - diag) / h;
+    I = r0 + (u - diag) % h;
+  }
 }
 
 // Arguments of one 3-way tally launch over all triples i < j < k.

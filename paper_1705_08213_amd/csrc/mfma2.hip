@@ -13,12 +13,13 @@ __global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tile
   constexpr int BM = 32 * WM, BN = 32 * WN;
   static_assert(BM == 2 * BN, "triangle split assumes BM = 2 BN");
   const int wave = threadIdx.x >> 6;
-  // XCD-contiguous runs of tiles: a run shares its row block in one L2
+  // XCD-contiguous runs of tiles (triangle: in strip order, so that a run
+  // shares row and column blocks in one L2)
   const int64_t b = xcd_unit(blockIdx.x, gridDim.x);
   int64_t I, J;
   if (a.tri) {
     int64_t sq_i, sq_j;
-    tri_tile((b >> 1) + a.sq_offset, tiles_side, sq_i, sq_j);
+    strip_square(b >> 1, tiles_side, a.row_begin / BM, (a.row_end + BM - 1) / BM, sq_i, sq_j);
     I = sq_i;
     J = 2 * sq_j + (b & 1);
   } else {
@@ -46,8 +47,7 @@ hipError_t launch_shape(const Pair2Args& a, hipStream_t stream) {
   Pair2Args b = a;
   if (a.tri) {  // squares of the row range, two halves each
     const int64_t s0 = a.row_begin / BM, s1 = (a.row_end + BM - 1) / BM;
-    b.sq_offset = s0 * tm - s0 * (s0 - 1) / 2;
-    ntiles = 2 * (s1 * tm - s1 * (s1 - 1) / 2 - b.sq_offset);
+    ntiles = 2 * (s1 * tm - s1 * (s1 - 1) / 2 - (s0 * tm - s0 * (s0 - 1) / 2));
   }
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;

@@ -2,7 +2,9 @@
 // the library's kernels.h, compiled for the host): for each case, the units
 // cover every triple i < j < k with i in [i_begin, min(i_end, n-2)) exactly
 // once, every unit lies inside its tile pair, and the XCD remap of a grid is
-// a permutation.  Prints "ok <cases>" and exits 0, or names the first failure.
+// a permutation.  Also the 2-way strip order of squares (strip_square) is a
+// one-to-one map onto each row range's squares.  Prints "ok <cases>" and
+// exits 0, or names the first failure.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -59,6 +61,24 @@ static int check(int64_t n, int64_t ib, int64_t ie, int64_t b) {
   return 0;
 }
 
+// The 2-way strip order of squares (strip_square): for a triangle of T
+// square rows and a row range [s0, s1), squares 0 .. count - 1 map one to
+// one onto the squares (I, J) with s0 <= I < s1 and I <= J < T.
+static int check_strips(int64_t T, int64_t s0, int64_t s1) {
+  const int64_t cnt = s1 * T - s1 * (s1 - 1) / 2 - (s0 * T - s0 * (s0 - 1) / 2);
+  std::vector<unsigned char> seen(T * T, 0);
+  for (int64_t t = 0; t < cnt; ++t) {
+    int64_t I, J;
+    strip_square(t, T, s0, s1, I, J);
+    if (I < s0 || I >= s1 || J < I || J >= T || seen[I * T + J]) {
+      printf("FAIL strip_square T=%ld s0=%ld s1=%ld t=%ld\n", (long)T, (long)s0, (long)s1, (long)t);
+      return 1;
+    }
+    seen[I * T + J] = 1;
+  }
+  return 0;
+}
+
 int main() {
   const long cases[][3] = {{3, 0, 3},      {4, 0, 4},      {5, 0, 5},     {64, 0, 64},
                            {65, 0, 65},    {66, 0, 66},    {130, 0, 130}, {150, 5, 64},
@@ -76,6 +96,14 @@ int main() {
     if (check(n, ib, ie, b)) return 1;
     ++count;
   }
+  for (int64_t T = 1; T <= 40; ++T)  // every row range of small triangles
+    for (int64_t s0 = 0; s0 < T; ++s0)
+      for (int64_t s1 = s0 + 1; s1 <= T; ++s1) {
+        if (check_strips(T, s0, s1)) return 1;
+        ++count;
+      }
+  if (check_strips(256, 0, 256) || check_strips(700, 93, 611)) return 1;  // the c2 shape, a ragged range
+  count += 2;
   printf("ok %d\n", count);
   return 0;
 }

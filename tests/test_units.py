@@ -1,6 +1,7 @@
-"""The 3-way work-unit enumeration of the library (tile-pair major, XCD
-remap), compiled for the host from the library's own header and checked by
-brute force: every staged triple is covered by exactly one unit."""
+"""The work enumerations of the library, compiled for the host from its own
+header and checked by brute force: the 3-way work units (tile-pair major, XCD
+remap) cover every staged triple exactly once, and the 2-way strip order of
+squares maps one to one onto each row range's squares."""
 import os
 import shutil
 import subprocess
