@@ -219,10 +219,11 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
   static_assert(BM % BN == 0, "square tiles split into whole column parts");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, rl = lane & 15;
-  // XCD-contiguous runs of tiles: a run shares its row block in one L2
+  // XCD-contiguous runs of squares in strip order: a run shares row and
+  // column blocks in one L2
   const int64_t b = xcd_unit(blockIdx.x, gridDim.x);
   int64_t sq_i, sq_j;
-  tri_tile(b / PARTS, tiles_side, sq_i, sq_j);
+  strip_square(b / PARTS, tiles_side, 0, tiles_side, sq_i, sq_j);
   const int64_t row0 = sq_i * BM + (wave & 1) * 16 * WM;
   const int64_t col0 = (sq_j * PARTS + b % PARTS) * BN + (wave >> 1) * 16 * WN;
   // a wave with no pair i < j does no MFMA work (in the fp4 form it still
