@@ -198,7 +198,7 @@ __device__ __forceinline__ void mma_superstep_rho1(const u4 (&pa)[WM], const u4 
 // V = sum P_i P_j give the table:
 //   C11 = S,  C10 = 2T - S,  C01 = 2U - S,  C00 = 4V - 2T - 2U + S
 // (rho(0) = 2P - rho(1)); the general 2-way loop reaches them through the
-// cheaper plane U = rho(1) + 2 [missing] (planes16_f4u).  Fields past n_f
+// cheaper plane U = rho(1) + 2 [missing] (planes32_f4u).  Fields past n_f
 // carry the missing code, which is zero in rho(1) and P.
 // ---------------------------------------------------------------------------
 
@@ -219,21 +219,43 @@ __device__ __forceinline__ void planes16_f4(unsigned w, unsigned (&r)[2], unsign
   p[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
 }
 
+// Elements q, q + 1 of a register array as a two-element array.
+__device__ __forceinline__ unsigned (&pair_of(unsigned (&x)[4], int q))[2] {
+  return *reinterpret_cast<unsigned(*)[2]>(&x[q]);
+}
+
 // The 2-way planes U = rho(1) + 2 [missing] (codes 00, 01, 10, 11 -> 0, 1,
-// 2, 2) and P of 16 fields as fp4 nibbles, in seven operations: even fields
+// 2, 2) and P of 16 fields (one word w) as fp4 nibbles, in seven operations: even fields
 // in the low two bits of a nibble (e2m1 value = plane / 2), odd fields in
 // its middle two bits (value = plane; U = 2 is the pattern 0100, never 0110).
 // With s = w >> 1, h = s & kEven2 (hi at bit 0 of each field, 0 at bit 1)
 // and q = h >> 1, truth tables 0x20 = c & a & ~b and 0xA2 = c & (a | ~b):
 //   ue: bit 0 = lo & ~hi, bit 1 = hi         uo: the same at bits 1, 2
 //   pe: bit 0 = lo | ~hi                     po: the same at bit 1
-__device__ __forceinline__ void planes16_f4u(unsigned w, unsigned& ue, unsigned& uo, unsigned& pe,
-                                             unsigned& po) {
-  const unsigned s = w >> 1, h = s & kEven2, q = h >> 1;
-  ue = __builtin_amdgcn_bitop3_b32(w, h, 0x33333333u, 0x20);
-  uo = __builtin_amdgcn_bitop3_b32(s, q, 0x66666666u, 0x20);
-  pe = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
-  po = __builtin_amdgcn_bitop3_b32(s, q, 0x22222222u, 0xA2);
+// Two words at once: the shifts s and q are taken on the 64-bit pair, one
+// v_lshrrev_b64 each (the bit that crosses from the upper word lands in bit
+// 31 of the lower one, which no mask keeps), six operations per word.
+// Written as inline asm: the compiler otherwise splits the 64-bit shift into
+// v_alignbit and a 32-bit shift, which saves nothing.
+__device__ __forceinline__ void planes32_f4u(unsigned w0, unsigned w1, unsigned (&ue)[2],
+                                             unsigned (&uo)[2], unsigned (&pe)[2],
+                                             unsigned (&po)[2]) {
+  const unsigned long long W = ((unsigned long long)w1 << 32) | w0;
+  unsigned long long S;
+  asm("v_lshrrev_b64 %0, 1, %1" : "=v"(S) : "v"(W));
+  const unsigned s0 = (unsigned)S, s1 = (unsigned)(S >> 32);
+  const unsigned h0 = s0 & kEven2, h1 = s1 & kEven2;
+  unsigned long long Q;
+  asm("v_lshrrev_b64 %0, 1, %1" : "=v"(Q) : "v"(((unsigned long long)h1 << 32) | h0));
+  const unsigned q0 = (unsigned)Q, q1 = (unsigned)(Q >> 32);
+  ue[0] = __builtin_amdgcn_bitop3_b32(w0, h0, 0x33333333u, 0x20);
+  ue[1] = __builtin_amdgcn_bitop3_b32(w1, h1, 0x33333333u, 0x20);
+  uo[0] = __builtin_amdgcn_bitop3_b32(s0, q0, 0x66666666u, 0x20);
+  uo[1] = __builtin_amdgcn_bitop3_b32(s1, q1, 0x66666666u, 0x20);
+  pe[0] = __builtin_amdgcn_bitop3_b32(w0, s0, 0x11111111u, 0xA2);
+  pe[1] = __builtin_amdgcn_bitop3_b32(w1, s1, 0x11111111u, 0xA2);
+  po[0] = __builtin_amdgcn_bitop3_b32(s0, q0, 0x22222222u, 0xA2);
+  po[1] = __builtin_amdgcn_bitop3_b32(s1, q1, 0x22222222u, 0xA2);
 }
 
 // fp4 MFMA with both E8M0 scales 2^(e - 127).
@@ -269,7 +291,7 @@ __device__ __forceinline__ v4f mfma_f4(const v8i& a, const v8i& b, v4f c) {
 __device__ __forceinline__ int f4_count(float x) { return (int)(4.0f * x); }
 
 // Table (entry 2a+b) from the four sums of the U and P planes
-// (planes16_f4u) over the K fields of the loop: rho(1) = U + 2P - 2 gives
+// (planes32_f4u) over the K fields of the loop: rho(1) = U + 2P - 2 gives
 //   S = UU + 2UP + 2PU + 4PP - 2 n_i(1) - 2 n_j(1) - 4K,
 //   T = UP + 2PP - 2 m_j,  U' = PU + 2PP - 2 m_i,  V = PP
 // (sum_q U_i = n_i(1) + 2 (K - m_i), sum_q P_i = m_i).
@@ -282,7 +304,7 @@ __device__ __forceinline__ v4i table_f4u(float uu, float up, float pu, float pp,
 }
 
 // One 256-field super-step of the four sums of the U and P planes
-// (planes16_f4u): the MFMA step of the even fields of the lane's four words,
+// (planes32_f4u): the MFMA step of the even fields of the lane's four words,
 // then the one of the odd fields, whose nibble values are twice as large
 // (scales 2^-1 on A and B).
 template <int WM, int WN>
@@ -293,7 +315,9 @@ __device__ __forceinline__ void mma_superstep_f4u(const u4 (&xa)[WM], const u4 (
   for (int n = 0; n < WN; ++n) {
     unsigned ue[4], uo[4], pe[4], po[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) planes16_f4u(word_of(xb[n], q), ue[q], uo[q], pe[q], po[q]);
+    for (int q = 0; q < 4; q += 2)
+      planes32_f4u(word_of(xb[n], q), word_of(xb[n], q + 1), pair_of(ue, q), pair_of(uo, q),
+                   pair_of(pe, q), pair_of(po, q));
     bu[0][n] = v8i{(int)ue[0], (int)ue[1], (int)ue[2], (int)ue[3], 0, 0, 0, 0};
     bu[1][n] = v8i{(int)uo[0], (int)uo[1], (int)uo[2], (int)uo[3], 0, 0, 0, 0};
     bp[0][n] = v8i{(int)pe[0], (int)pe[1], (int)pe[2], (int)pe[3], 0, 0, 0, 0};
@@ -303,7 +327,9 @@ __device__ __forceinline__ void mma_superstep_f4u(const u4 (&xa)[WM], const u4 (
   for (int m = 0; m < WM; ++m) {
     unsigned ue[4], uo[4], pe[4], po[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) planes16_f4u(word_of(xa[m], q), ue[q], uo[q], pe[q], po[q]);
+    for (int q = 0; q < 4; q += 2)
+      planes32_f4u(word_of(xa[m], q), word_of(xa[m], q + 1), pair_of(ue, q), pair_of(uo, q),
+                   pair_of(pe, q), pair_of(po, q));
     const v8i au0{(int)ue[0], (int)ue[1], (int)ue[2], (int)ue[3], 0, 0, 0, 0};
     const v8i ap0{(int)pe[0], (int)pe[1], (int)pe[2], (int)pe[3], 0, 0, 0, 0};
     const v8i au1{(int)uo[0], (int)uo[1], (int)uo[2], (int)uo[3], 0, 0, 0, 0};
