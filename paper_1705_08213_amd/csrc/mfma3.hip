@@ -98,6 +98,40 @@ __device__ __forceinline__ void j_masks_f4(unsigned w, unsigned* y, unsigned* sg
   }
 }
 
+// j_masks_f4 of two words w0 (into y[0..1], sg[0..1], p[0..1]) and w1 (into
+// y[2..3] ...), with the shifts paired (twenty-five operations instead of
+// thirty).  Crossing bits: s takes w1's bit 0 into bit 31, which every mask
+// drops; the >> 2 moves bits that sit at 2 mod 4 (w1's bits 0-1 are zero);
+// the << 3 and << 1 move bits that sit at 0 mod 4 and 2 mod 4 (w0's bits
+// 29-31 are zero).
+__device__ __forceinline__ void j_masks32_f4(unsigned w0, unsigned w1, unsigned* y, unsigned* sg,
+                                             unsigned* p) {
+  unsigned s0, s1, a, b;
+  tile2::shr_pair<1>(w0, w1, s0, s1);
+  unsigned t0 = __builtin_amdgcn_bitop3_b32(w0, s0, 0x11111111u, 0x82);
+  unsigned t1 = __builtin_amdgcn_bitop3_b32(w1, s1, 0x11111111u, 0x82);
+  y[0] = t0 | (t0 << 1);
+  y[2] = t1 | (t1 << 1);
+  tile2::shr_pair<2>(__builtin_amdgcn_bitop3_b32(w0, s0, 0x44444444u, 0x82),
+                     __builtin_amdgcn_bitop3_b32(w1, s1, 0x44444444u, 0x82), a, b);
+  y[1] = a | (a << 1);
+  y[3] = b | (b << 1);
+  tile2::shl_pair<3>(__builtin_amdgcn_bitop3_b32(w0, s0, 0x11111111u, 0x02),
+                     __builtin_amdgcn_bitop3_b32(w1, s1, 0x11111111u, 0x02), sg[0], sg[2]);
+  tile2::shl_pair<1>(__builtin_amdgcn_bitop3_b32(w0, s0, 0x44444444u, 0x02),
+                     __builtin_amdgcn_bitop3_b32(w1, s1, 0x44444444u, 0x02), sg[1], sg[3]);
+  if (p) {
+    t0 = __builtin_amdgcn_bitop3_b32(w0, s0, 0x11111111u, 0xA2);
+    t1 = __builtin_amdgcn_bitop3_b32(w1, s1, 0x11111111u, 0xA2);
+    p[0] = t0 | (t0 << 1);
+    p[2] = t1 | (t1 << 1);
+    tile2::shr_pair<2>(__builtin_amdgcn_bitop3_b32(w0, s0, 0x44444444u, 0xA2),
+                       __builtin_amdgcn_bitop3_b32(w1, s1, 0x44444444u, 0xA2), a, b);
+    p[1] = a | (a << 1);
+    p[3] = b | (b << 1);
+  }
+}
+
 // (z & m) ^ sg: z modulated by D_j.
 __device__ __forceinline__ unsigned mod_d(unsigned z, unsigned m, unsigned sg) {
   return __builtin_amdgcn_bitop3_b32(z, m, sg, 0x6A);
@@ -146,22 +180,19 @@ __device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j,
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       unsigned y[4], sg[4], pm[4];
-      j_masks_f4(word_of(xj, 2 * h), y, sg, pm);
-      j_masks_f4(word_of(xj, 2 * h + 1), y + 2, sg + 2, pm + 2);
+      j_masks32_f4(word_of(xj, 2 * h), word_of(xj, 2 * h + 1), y, sg, pm);
       v8i AR[WI], AP[WI];
 #pragma unroll
       for (int m = 0; m < WI; ++m) {
         unsigned r0[2], p0[2], r1[2], p1[2];
-        tile2::planes16_f4(word_of(xa[m], 2 * h), r0, p0);
-        tile2::planes16_f4(word_of(xa[m], 2 * h + 1), r1, p1);
+        tile2::planes32_f4(word_of(xa[m], 2 * h), word_of(xa[m], 2 * h + 1), r0, p0, r1, p1);
         AR[m] = tile2::operand_f4(r0, r1);
         AP[m] = tile2::operand_f4(p0, p1);
       }
 #pragma unroll
       for (int c = 0; c < WK; ++c) {
         unsigned r0[2], p0[2], r1[2], p1[2];
-        tile2::planes16_f4(word_of(xk[c], 2 * h), r0, p0);
-        tile2::planes16_f4(word_of(xk[c], 2 * h + 1), r1, p1);
+        tile2::planes32_f4(word_of(xk[c], 2 * h), word_of(xk[c], 2 * h + 1), r0, p0, r1, p1);
         const unsigned R[4] = {r0[0], r0[1], r1[0], r1[1]};
         const unsigned P[4] = {p0[0], p0[1], p1[0], p1[1]};
         v8i B[4];  // y z = D R, D P, P R, P P

@@ -205,18 +205,53 @@ __device__ __forceinline__ void mma_superstep_rho1(const u4 (&pa)[WM], const u4 
 constexpr unsigned kEven2 = 0x55555555u;  // bit 0 of every 2-bit field
 constexpr unsigned kNib2 = 0x33333333u;   // low two bits of every nibble
 
-// The rho(1) and P planes of 16 fields as one fp4 operand half each:
-// r = (rho(1) of even fields, of odd fields), p likewise (see nibbles32).
-// Ten operations: v_bitop3 truth tables 0x80 = a & b & c and
-// 0xA2 = c & (a | ~b) (with a = w, b = w >> 1: bit 0 of a field is lo, of
-// b is hi).
-__device__ __forceinline__ void planes16_f4(unsigned w, unsigned (&r)[2], unsigned (&p)[2]) {
-  const unsigned s = w >> 1;
-  const unsigned r1 = (w & kEven2) + __builtin_amdgcn_bitop3_b32(w, s, kEven2, 0x80);
-  r[0] = r1 & kNib2;
-  r[1] = (r1 >> 2) & kNib2;
-  p[0] = __builtin_amdgcn_bitop3_b32(w, s, 0x11111111u, 0xA2);
-  p[1] = __builtin_amdgcn_bitop3_b32(w, s, 0x44444444u, 0xA2) >> 2;
+// Shifts of a pair of words as one 64-bit shift (v_lshrrev_b64 /
+// v_lshlrev_b64, as inline asm: the compiler would split them).  Callers
+// use them only where the bits crossing between the words are zero or
+// masked off afterwards.
+template <int N>
+__device__ __forceinline__ void shr_pair(unsigned a0, unsigned a1, unsigned& r0, unsigned& r1) {
+  const unsigned long long x = ((unsigned long long)a1 << 32) | a0;
+  unsigned long long y;
+  asm("v_lshrrev_b64 %0, %1, %2" : "=v"(y) : "n"(N), "v"(x));
+  r0 = (unsigned)y;
+  r1 = (unsigned)(y >> 32);
+}
+template <int N>
+__device__ __forceinline__ void shl_pair(unsigned a0, unsigned a1, unsigned& r0, unsigned& r1) {
+  const unsigned long long x = ((unsigned long long)a1 << 32) | a0;
+  unsigned long long y;
+  asm("v_lshlrev_b64 %0, %1, %2" : "=v"(y) : "n"(N), "v"(x));
+  r0 = (unsigned)y;
+  r1 = (unsigned)(y >> 32);
+}
+
+// The rho(1) and P planes of two words w0, w1 as fp4 operand halves: r0 =
+// (rho(1) of w0's even fields, of its odd fields), p0 likewise, r1 and p1
+// for w1 (see nibbles32).  v_bitop3 truth tables 0x80 = a & b & c and
+// 0xA2 = c & (a | ~b) (with a = w, b = w >> 1: bit 0 of a field is lo, of b
+// is hi).  Seventeen operations, the shifts paired (twenty one word at a
+// time).  Crossing bits: s takes
+// w1's bit 0 into bit 31, which every mask drops; the >> 2 of r and of the
+// odd P bits takes w1's bits 0-1 into bits 30-31, dropped by kNib2 for r and
+// zero for P (its bits sit at 2 mod 4).
+__device__ __forceinline__ void planes32_f4(unsigned w0, unsigned w1, unsigned (&r0)[2],
+                                            unsigned (&p0)[2], unsigned (&r1)[2],
+                                            unsigned (&p1)[2]) {
+  unsigned s0, s1;
+  shr_pair<1>(w0, w1, s0, s1);
+  const unsigned a0 = (w0 & kEven2) + __builtin_amdgcn_bitop3_b32(w0, s0, kEven2, 0x80);
+  const unsigned a1 = (w1 & kEven2) + __builtin_amdgcn_bitop3_b32(w1, s1, kEven2, 0x80);
+  unsigned b0, b1;
+  shr_pair<2>(a0, a1, b0, b1);
+  r0[0] = a0 & kNib2;
+  r0[1] = b0 & kNib2;
+  r1[0] = a1 & kNib2;
+  r1[1] = b1 & kNib2;
+  p0[0] = __builtin_amdgcn_bitop3_b32(w0, s0, 0x11111111u, 0xA2);
+  p1[0] = __builtin_amdgcn_bitop3_b32(w1, s1, 0x11111111u, 0xA2);
+  shr_pair<2>(__builtin_amdgcn_bitop3_b32(w0, s0, 0x44444444u, 0xA2),
+              __builtin_amdgcn_bitop3_b32(w1, s1, 0x44444444u, 0xA2), p0[1], p1[1]);
 }
 
 // Elements q, q + 1 of a register array as a two-element array.
@@ -232,22 +267,16 @@ __device__ __forceinline__ unsigned (&pair_of(unsigned (&x)[4], int q))[2] {
 // and q = h >> 1, truth tables 0x20 = c & a & ~b and 0xA2 = c & (a | ~b):
 //   ue: bit 0 = lo & ~hi, bit 1 = hi         uo: the same at bits 1, 2
 //   pe: bit 0 = lo | ~hi                     po: the same at bit 1
-// Two words at once: the shifts s and q are taken on the 64-bit pair, one
-// v_lshrrev_b64 each (the bit that crosses from the upper word lands in bit
-// 31 of the lower one, which no mask keeps), six operations per word.
-// Written as inline asm: the compiler otherwise splits the 64-bit shift into
-// v_alignbit and a 32-bit shift, which saves nothing.
+// Two words at once: the shifts s and q are taken on the 64-bit pair
+// (shr_pair: the bit that crosses from the upper word lands in bit 31 of the
+// lower one, which no mask keeps), six operations per word.
 __device__ __forceinline__ void planes32_f4u(unsigned w0, unsigned w1, unsigned (&ue)[2],
                                              unsigned (&uo)[2], unsigned (&pe)[2],
                                              unsigned (&po)[2]) {
-  const unsigned long long W = ((unsigned long long)w1 << 32) | w0;
-  unsigned long long S;
-  asm("v_lshrrev_b64 %0, 1, %1" : "=v"(S) : "v"(W));
-  const unsigned s0 = (unsigned)S, s1 = (unsigned)(S >> 32);
+  unsigned s0, s1, q0, q1;
+  shr_pair<1>(w0, w1, s0, s1);
   const unsigned h0 = s0 & kEven2, h1 = s1 & kEven2;
-  unsigned long long Q;
-  asm("v_lshrrev_b64 %0, 1, %1" : "=v"(Q) : "v"(((unsigned long long)h1 << 32) | h0));
-  const unsigned q0 = (unsigned)Q, q1 = (unsigned)(Q >> 32);
+  shr_pair<1>(h0, h1, q0, q1);
   ue[0] = __builtin_amdgcn_bitop3_b32(w0, h0, 0x33333333u, 0x20);
   ue[1] = __builtin_amdgcn_bitop3_b32(w1, h1, 0x33333333u, 0x20);
   uo[0] = __builtin_amdgcn_bitop3_b32(s0, q0, 0x66666666u, 0x20);
