@@ -403,22 +403,32 @@ __device__ __forceinline__ void wg_loop_f4(const Pair2Args& a, int64_t I0, int64
                                            const uint8_t* const (&pb)[WN],
                                            u4 (*stage)[2 * WM + 2 * WN][64], Step step) {
   constexpr int NB = 2 * WM + 2 * WN, BPW = (NB + 3) / 4;  // blocks, blocks per wave
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
   const int g = lane >> 4, rl = lane & 15;
-  const uint8_t* src[BPW];
+  // each copy: a wave-uniform base (the block's first row, clamped; its two
+  // halves read from lane 0 so the compiler knows it is uniform) plus a
+  // fixed 32-bit lane offset.  The LDS destinations become scalar (m0 set
+  // without v_readfirstlane).
+  const uint8_t* base[BPW];
+  uint32_t off[BPW];
 #pragma unroll
   for (int t = 0; t < BPW; ++t) {
     const int b = BPW * wave + t;  // blocks 0 .. 2 WM - 1 are rows i, then rows j
-    int64_t r = b < 2 * WM ? I0 + 16 * b + rl : J0 + 16 * (b - 2 * WM) + rl;
-    if (b < 2 * WM)
-      src[t] = a.va + (r < a.n_a ? r : a.n_a - 1) * a.lda + 16 * g;
-    else
-      src[t] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
+    const bool rows_i = b < 2 * WM;
+    const int64_t n = rows_i ? a.n_a : a.n_b, ld = rows_i ? a.lda : a.ldb;
+    const int64_t r0 = rows_i ? I0 + 16 * b : J0 + 16 * (b - 2 * WM);
+    const int64_t rf = r0 < n ? r0 : n - 1, r = r0 + rl < n ? r0 + rl : n - 1;
+    const uint64_t bp = (uint64_t)((rows_i ? a.va : a.vb) + rf * ld);  // uniform
+    base[t] = (const uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32))
+                                << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
+    off[t] = (uint32_t)((r - rf) * ld + 16 * g);
   }
   auto issue = [&](int64_t s, int buf) {
 #pragma unroll
     for (int t = 0; t < BPW; ++t)
-      if (BPW * wave + t < NB) stage_row(src[t] + s * 64, &stage[buf][BPW * wave + t][0]);
+      if (BPW * wave + t < NB) stage_row(base[t] + s * 64 + off[t], &stage[buf][BPW * wave + t][0]);
   };
   const int ma = (wave & 1) * WM, nb = 2 * WM + (wave >> 1) * WN;
   const int64_t nfull = a.n_f / 256, nbytes = (a.n_f + 3) / 4;
