@@ -226,18 +226,30 @@ __device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j,
   constexpr int NB = 2 * WI + 2 * WK + 1, BPW = (NB + 3) / 4;
   auto stage = reinterpret_cast<u4(*)[NB][64]>(lds);
   const int64_t I0 = row0 - (wave & 1) * 16 * WI, K0 = col0 - (wave >> 1) * 16 * WK;
-  const uint8_t* src[BPW];
+  // each copy: a wave-uniform base (the block's first row, clamped; read
+  // from lane 0 so the compiler knows it is uniform) plus a fixed 32-bit
+  // lane offset (the j block: 16 copies of row j)
+  const int wu = __builtin_amdgcn_readfirstlane(wave);
+  const uint8_t* base[BPW];
+  uint32_t off[BPW];
 #pragma unroll
   for (int t = 0; t < BPW; ++t) {
-    const int b = BPW * wave + t;
-    int64_t r = b < 2 * WI ? I0 + 16 * b + rl : (b < NB - 1 ? K0 + 16 * (b - 2 * WI) + rl : j);
-    src[t] = a.v + (r < n ? r : n - 1) * a.ld + 16 * g;
+    const int b = BPW * wu + t;
+    const int64_t r0 = b < 2 * WI ? I0 + 16 * b : (b < NB - 1 ? K0 + 16 * (b - 2 * WI) : j);
+    const int64_t r1 = b < NB - 1 ? r0 + rl : j;
+    const int64_t rf = r0 < n ? r0 : n - 1, r = r1 < n ? r1 : n - 1;
+    const uint64_t bp = (uint64_t)(a.v + rf * a.ld);
+    base[t] = (const uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32))
+                                << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
+    off[t] = (uint32_t)((r - rf) * a.ld + 16 * g);
   }
   const int64_t nfull = a.n_f / 256;
   auto issue = [&](int64_t st, int buf) {
 #pragma unroll
     for (int t = 0; t < BPW; ++t)
-      if (BPW * wave + t < NB) tile2::stage_row(src[t] + st * 64, &stage[buf][BPW * wave + t][0]);
+      if (BPW * wu + t < NB)
+        tile2::stage_row(base[t] + st * 64 + off[t], &stage[buf][BPW * wu + t][0]);
   };
   const int ia = (wave & 1) * WI, kb = 2 * WI + (wave >> 1) * WK;
   if (nfull > 0) issue(0, 0);

@@ -263,13 +263,22 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
     static_assert(ND % 4 == 0, "the piece copies split evenly over the waves");
     __shared__ u4 stage[2][ND][64];  // piece 2 blk + h; A blocks first, then B
     const int64_t I0 = sq_i * BM, J0 = (sq_j * PARTS + b % PARTS) * BN;
-    const uint8_t* src[DPW];
+    // each copy: a wave-uniform base (the block's first row, clamped; read
+    // from lane 0 so the compiler knows it is uniform) plus a fixed 32-bit
+    // lane offset
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    const uint8_t* base[DPW];
+    uint32_t off[DPW];
 #pragma unroll
     for (int q = 0; q < DPW; ++q) {
-      const int d = wave + 4 * q, blk = d >> 1, h = d & 1;
-      int64_t r = blk < 2 * WM ? I0 + 16 * blk + rl : J0 + 16 * (blk - 2 * WM) + rl;
-      r = r < a.n ? r : a.n - 1;
-      src[q] = a.v + r * a.ld + 32 * g + 16 * h;
+      const int d = wu + 4 * q, blk = d >> 1, h = d & 1;
+      const int64_t r0 = blk < 2 * WM ? I0 + 16 * blk : J0 + 16 * (blk - 2 * WM);
+      const int64_t rf = r0 < a.n ? r0 : a.n - 1, r = r0 + rl < a.n ? r0 + rl : a.n - 1;
+      const uint64_t bp = (uint64_t)(a.v + rf * a.ld);
+      base[q] = (const uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32))
+                                  << 32) |
+                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
+      off[q] = (uint32_t)((r - rf) * a.ld + 32 * g + 16 * h);
     }
     const int ablk = (wave & 1) * WM, bblk = 2 * WM + (wave >> 1) * WN;
     // row(side, r, h) gives piece h of this wave's row block r of side 0 (A) or 1 (B)
@@ -291,7 +300,8 @@ __global__ __launch_bounds__(256, 2) void multi2_kernel(Multi2Args a, int64_t ti
     const int64_t nfull = a.n_f / 128;
     auto issue = [&](int64_t st, int buf) {
 #pragma unroll
-      for (int q = 0; q < DPW; ++q) tile2::stage_row(src[q] + st * 128, &stage[buf][wave + 4 * q][0]);
+      for (int q = 0; q < DPW; ++q)
+        tile2::stage_row(base[q] + st * 128 + off[q], &stage[buf][wu + 4 * q][0]);
     };
     if (nfull > 0) issue(0, 0);
     for (int64_t st = 0; st < nfull; ++st) {
