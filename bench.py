@@ -428,8 +428,8 @@ def main():
                          "to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps(dict(error="this benchmark runs on exactly one GPU; multi-GPU "
-                                    "sharding is not part of this build", n_gpus=args.gpus)))
+        print(json.dumps(dict(error="this benchmark runs on exactly one GPU; the library "
+                                    "has no multi-GPU sharding", n_gpus=args.gpus)))
         sys.exit(2)
     import torch
     import paper_1705_08213_amd as ccc
