@@ -40,6 +40,33 @@ def test_2way_rows_concatenate_to_the_triangle(path):
 
 
 @pytest.mark.parametrize("path", PATHS)
+def test_2way_rows_across_square_strips(path):
+    # 1500 rows are 12 square rows of 128: the MFMA launch walks them in
+    # strips of 8 (one whole, one partial); ranges start and end inside strips
+    import torch
+    n, n_f = 1500, 300
+    say("2way rows across strips", path)
+    v = synth.beta_hw(n, n_f, seed=907, missing=0.02)
+    dv = dev(v)
+    t_full, c_full, _ = ccc.ccc_2way(dv, n_f, path=path)
+    sync()
+    ot, oc = oracle.two_way(v, n_f)
+    assert_tables_equal(host(t_full), ot)
+    assert_ccc_close(host(c_full), oc)
+    parts = []
+    for i0, i1 in [(0, 700), (700, 1030), (1030, 1100), (1100, 1500)]:
+        t, c, _ = ccc.ccc_2way_rows(dv, n_f, i0, i1, path=path)
+        sync()
+        ot, oc = oracle.two_way(v, n_f, i0, i1)
+        assert_tables_equal(host(t), ot)
+        assert_ccc_close(host(c), oc)
+        if i1 > i0:
+            parts.append((t, c))
+    assert torch.equal(torch.cat([p[0] for p in parts]), t_full)
+    assert torch.equal(torch.cat([p[1] for p in parts]), c_full)
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_3way_rows_concatenate_to_the_tetrahedron(path):
     import torch
     n, n_f = 90, 700
