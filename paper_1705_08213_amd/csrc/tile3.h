@@ -125,13 +125,15 @@ __device__ __forceinline__ void emit_triple_staged(const Triple3Args& a, bool va
   }
   // the wave's LDS accesses run in program order; keep the compiler to it
   asm volatile("" ::: "memory");
+  // streaming stores: each instruction writes whole lines of output that is
+  // written once and not read back here
   if (a.tables) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int piece = 16 * q + rl;
       const u4 d = T[piece];
       if ((gm >> (piece >> 1)) & 1u)
-        reinterpret_cast<u4*>(a.tables + 8 * p0)[piece] = d;
+        __builtin_nontemporal_store(d, reinterpret_cast<u4*>(a.tables + 8 * p0) + piece);
     }
   }
   if (a.ccc) {
@@ -139,7 +141,8 @@ __device__ __forceinline__ void emit_triple_staged(const Triple3Args& a, bool va
     for (int q = 0; q < 4; ++q) {
       const int piece = 16 * q + rl;
       const u4 d = C[piece];
-      if ((gm >> (piece >> 2)) & 1u) reinterpret_cast<u4*>(a.ccc + 8 * p0)[piece] = d;
+      if ((gm >> (piece >> 2)) & 1u)
+        __builtin_nontemporal_store(d, reinterpret_cast<u4*>(a.ccc + 8 * p0) + piece);
     }
   }
   asm volatile("" ::: "memory");  // the scratch is reused by the next call
