@@ -22,7 +22,9 @@
  * missing entry (the marker the paper's future-work section sets aside).  Bits
  * past n_f are ignored whatever they hold.  Only the first ceil(n_f/4) bytes
  * of each row, rounded up to a multiple of 16, are ever read, so a row pointer
- * may point into a wider row (a field chunk) whose stride is ld.
+ * may point into a wider row (a field chunk) whose stride is ld.  The kernels
+ * address a 16-row block of the input with 32-bit offsets, so ld (bytes) is
+ * at most 2^28 (CCC_ERR_RANGE beyond; ccc_2way_multi likewise).
  *
  * Missing data: a missing entry contributes to no tally; m_i counts the
  * present fields of vector i, m_ij (m_ijk) the fields where every vector of
@@ -81,21 +83,28 @@ enum {
 };
 
 /*
- * Operand formats of the MFMA path.  Every MFMA call (ccc_2way, ccc_3way,
- * their _rows, _select, _block and _many forms, and ccc_2way_multi) takes
- * fp4 (e2m1) operands with fp32 accumulation while n_f <= 2^22 (a batch of
- * ccc_2way_many: while every problem's n_f is), int8 operands with int32
- * accumulation beyond.  The fp4 operands are per-allele planes halved
- * (rho(a)/2, P/2 with P = 1 for a present entry, and for the 3-way middle
- * vector (rho(1) - P)/2), values 0, +-1/2 and 1, each exact in e2m1; every
- * partial sum is a multiple of 1/4 of magnitude at most n_f, so below 2^22
- * fp32 holds it exactly and the tables are the same exact integers as with
- * int8.
+ * Operand formats of the MFMA path (ccc_opts.operands).  Both give the same
+ * exact integer tables; they differ in speed and range.
+ *  - CCC_OPERANDS_INT8: per-allele counts rho(a) in {0,1,2} (or planes built
+ *    from them) as int8 operands with int32 accumulation -- the paper's
+ *    modified-GEMM tally (Sec. 3.1) on the int8 matrix cores.  Valid for
+ *    every n_f the call accepts.
+ *  - CCC_OPERANDS_FP4: the same planes halved (rho(a)/2, P/2 with P = 1 for
+ *    a present entry, and for the 3-way middle vector (rho(1) - P)/2), values
+ *    0, +-1/2 and 1, each exact in e2m1, with fp32 accumulation at twice the
+ *    int8 rate.  Every partial sum is a multiple of 1/4 of magnitude at most
+ *    n_f, so fp32 holds it exactly while n_f <= 2^22 (a batch of
+ *    ccc_2way_many: while every problem's n_f is; a chunk of ccc_2way_block:
+ *    while the chunk's n_f is).  Beyond that the call returns CCC_ERR_RANGE.
+ *  - CCC_OPERANDS_AUTO (0): fp4 while n_f <= 2^22, int8 beyond.
+ * With CCC_PATH_POPCOUNT the field must be CCC_OPERANDS_AUTO (else
+ * CCC_ERR_ARG).
  */
-enum { CCC_OPERANDS_FP4 = 4, CCC_OPERANDS_INT8 = 8 };
+enum { CCC_OPERANDS_AUTO = 0, CCC_OPERANDS_FP4 = 4, CCC_OPERANDS_INT8 = 8 };
 
-/* CCC_OPERANDS_* of an MFMA call over n_f fields (host only, no device
- * work); CCC_ERR_ARG for n_f < 0. */
+/* CCC_OPERANDS_FP4 or _INT8: the format an MFMA call over n_f fields takes
+ * with CCC_OPERANDS_AUTO (host only, no device work); CCC_ERR_ARG for
+ * n_f < 0. */
 int ccc_mfma_operands(int64_t n_f);
 
 /* Flags for ccc_2way_block (field-chunked use). */
@@ -108,9 +117,11 @@ typedef struct {
   int path;       /* CCC_PATH_* */
   double gamma;   /* the constant of Eqs. (3)-(4); the paper uses 2/3 */
   unsigned flags; /* CCC_ACCUMULATE | CCC_FINALIZE (ccc_2way_block only) */
+  int operands;   /* CCC_OPERANDS_* (MFMA path only; AUTO otherwise) */
 } ccc_opts;
 
-/* Options used when `opts` is NULL: CCC_PATH_AUTO, gamma = 2/3, flags 0. */
+/* Options used when `opts` is NULL: CCC_PATH_AUTO, gamma = 2/3, flags 0,
+ * CCC_OPERANDS_AUTO. */
 ccc_opts ccc_default_opts(void);
 
 /*
@@ -276,7 +287,9 @@ void ccc_release_workspace(void);
  * Kernel timing (profiling aid, off by default).  While enabled, the library
  * records a pair of HIP events on the launching stream around each tally
  * kernel launch; names are "count1", "pop2", "mfma2", "pop3", "mfma3",
- * "multi2".
+ * "multi2", and "many" around a ccc_2way_many launch (its graph replay).
+ * "many_setup" is a host-side duration: building a new batch's work list,
+ * uploading it, and capturing and instantiating its graph.
  * Do not enable it while a stream is being captured into a graph.
  *   ccc_timing_query: total milliseconds and number of recorded launches of
  *   kernel `name` (NULL = all); waits for the recorded events.

@@ -23,11 +23,13 @@ CCC_OK, CCC_ERR_ARG, CCC_ERR_RANGE, CCC_ERR_ALIGN = 0, -1, -2, -3
 CCC_ERR_HIP, CCC_ERR_NOMEM, CCC_ERR_UNSUPPORTED = -4, -5, -6
 CCC_PATH_AUTO, CCC_PATH_POPCOUNT, CCC_PATH_MFMA = 0, 1, 2
 CCC_ACCUMULATE, CCC_FINALIZE = 1, 2
+CCC_OPERANDS_AUTO, CCC_OPERANDS_FP4, CCC_OPERANDS_INT8 = 0, 4, 8
 GAMMA = 2.0 / 3.0
 
 _PATHS = {"auto": CCC_PATH_AUTO, "popcount": CCC_PATH_POPCOUNT, "mfma": CCC_PATH_MFMA,
           CCC_PATH_AUTO: CCC_PATH_AUTO, CCC_PATH_POPCOUNT: CCC_PATH_POPCOUNT,
           CCC_PATH_MFMA: CCC_PATH_MFMA}
+_OPERANDS = {"auto": CCC_OPERANDS_AUTO, "fp4": CCC_OPERANDS_FP4, "int8": CCC_OPERANDS_INT8}
 
 
 class CccError(RuntimeError):
@@ -37,7 +39,8 @@ class CccError(RuntimeError):
 
 
 class ccc_opts(ctypes.Structure):
-    _fields_ = [("path", ctypes.c_int), ("gamma", ctypes.c_double), ("flags", ctypes.c_uint)]
+    _fields_ = [("path", ctypes.c_int), ("gamma", ctypes.c_double), ("flags", ctypes.c_uint),
+                ("operands", ctypes.c_int)]
 
 
 class ccc_selection(ctypes.Structure):
@@ -116,11 +119,13 @@ def release_workspace() -> None:
     lib().ccc_release_workspace()
 
 
-def make_opts(path="auto", gamma=GAMMA, flags=0) -> ccc_opts:
-    """Options struct; ``path`` is a name or a raw integer (passed through, so
-    the library's own validation can be exercised)."""
+def make_opts(path="auto", gamma=GAMMA, flags=0, operands="auto") -> ccc_opts:
+    """Options struct; ``path`` ("auto", "popcount", "mfma") and ``operands``
+    ("auto", "fp4", "int8": the MFMA operand format) are names or raw integers
+    (passed through, so the library's own validation can be exercised)."""
     p = _PATHS[path] if isinstance(path, str) else int(path)
-    return ccc_opts(p, float(gamma), int(flags))
+    o = _OPERANDS[operands] if isinstance(operands, str) else int(operands)
+    return ccc_opts(p, float(gamma), int(flags), o)
 
 
 # ---------------------------------------------------------------------------
@@ -172,7 +177,7 @@ def n_triples(n: int) -> int:
 
 
 def ccc_2way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
-             want_tables=True, want_ccc=True, stream=None):
+             want_tables=True, want_ccc=True, stream=None, operands="auto"):
     """All pairs i<j: returns (tables int32 [P,4], ccc float64 [P,4], counts int32 [n_v,4])."""
     torch = _torch()
     _check_input(v)
@@ -188,7 +193,7 @@ def ccc_2way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMM
     _check_out(tables, (P, 4), torch.int32, "tables")
     _check_out(ccc, (P, 4), torch.float64, "ccc")
     _check_out(counts, (n_v, 4), torch.int32, "counts")
-    o = make_opts(path, gamma)
+    o = make_opts(path, gamma, operands=operands)
     st = lib().ccc_2way(_ptr(v), n_v, n_f, ld, _ptr(tables), _ptr(ccc), _ptr(counts),
                         ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_2way")
@@ -196,7 +201,7 @@ def ccc_2way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMM
 
 
 def ccc_2way_multi(v, n_f, s, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
-                   want_tables=True, want_ccc=True, stream=None):
+                   want_tables=True, want_ccc=True, stream=None, operands="auto"):
     """Multi-allelic pairs i<j over s = 2..4 states (one byte per field, bits
     2a..2a+1 = copies of state a, 0 = missing): returns (tables int32 [P, s*s],
     ccc float64 [P, s*s], counts int32 [n_v, 8])."""
@@ -215,7 +220,7 @@ def ccc_2way_multi(v, n_f, s, tables=None, ccc=None, counts=None, path="auto", g
     _check_out(tables, (P, ss), torch.int32, "tables")
     _check_out(ccc, (P, ss), torch.float64, "ccc")
     _check_out(counts, (n_v, 8), torch.int32, "counts")
-    o = make_opts(path, gamma)
+    o = make_opts(path, gamma, operands=operands)
     st = lib().ccc_2way_multi(_ptr(v), n_v, n_f, ld, s, _ptr(tables), _ptr(ccc), _ptr(counts),
                               ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_2way_multi")
@@ -223,7 +228,7 @@ def ccc_2way_multi(v, n_f, s, tables=None, ccc=None, counts=None, path="auto", g
 
 
 def ccc_3way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
-             want_tables=True, want_ccc=True, stream=None):
+             want_tables=True, want_ccc=True, stream=None, operands="auto"):
     """All triples i<j<k: returns (tables int32 [T,8], ccc float64 [T,8], counts)."""
     torch = _torch()
     _check_input(v)
@@ -239,7 +244,7 @@ def ccc_3way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMM
     _check_out(tables, (T, 8), torch.int32, "tables")
     _check_out(ccc, (T, 8), torch.float64, "ccc")
     _check_out(counts, (n_v, 4), torch.int32, "counts")
-    o = make_opts(path, gamma)
+    o = make_opts(path, gamma, operands=operands)
     st = lib().ccc_3way(_ptr(v), n_v, n_f, ld, _ptr(tables), _ptr(ccc), _ptr(counts),
                         ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_3way")
@@ -257,7 +262,7 @@ def triple_run_length(n_v: int, i_begin: int, i_end: int) -> int:
 
 
 def ccc_2way_rows(v, n_f, i_begin, i_end, tables=None, ccc=None, counts=None, path="auto",
-                  gamma=GAMMA, want_tables=True, want_ccc=True, stream=None):
+                  gamma=GAMMA, want_tables=True, want_ccc=True, stream=None, operands="auto"):
     """Pairs with first index in [i_begin, i_end), in lexicographic order."""
     torch = _torch()
     _check_input(v)
@@ -272,7 +277,7 @@ def ccc_2way_rows(v, n_f, i_begin, i_end, tables=None, ccc=None, counts=None, pa
         counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
     _check_out(tables, (P, 4), torch.int32, "tables")
     _check_out(ccc, (P, 4), torch.float64, "ccc")
-    o = make_opts(path, gamma)
+    o = make_opts(path, gamma, operands=operands)
     st = lib().ccc_2way_rows(_ptr(v), n_v, n_f, ld, i_begin, i_end, _ptr(tables), _ptr(ccc),
                              _ptr(counts), ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_2way_rows")
@@ -280,7 +285,7 @@ def ccc_2way_rows(v, n_f, i_begin, i_end, tables=None, ccc=None, counts=None, pa
 
 
 def ccc_3way_rows(v, n_f, i_begin, i_end, tables=None, ccc=None, counts=None, path="auto",
-                  gamma=GAMMA, want_tables=True, want_ccc=True, stream=None):
+                  gamma=GAMMA, want_tables=True, want_ccc=True, stream=None, operands="auto"):
     """Triples with first index in [i_begin, i_end), in lexicographic order."""
     torch = _torch()
     _check_input(v)
@@ -295,14 +300,15 @@ def ccc_3way_rows(v, n_f, i_begin, i_end, tables=None, ccc=None, counts=None, pa
         counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
     _check_out(tables, (T, 8), torch.int32, "tables")
     _check_out(ccc, (T, 8), torch.float64, "ccc")
-    o = make_opts(path, gamma)
+    o = make_opts(path, gamma, operands=operands)
     st = lib().ccc_3way_rows(_ptr(v), n_v, n_f, ld, i_begin, i_end, _ptr(tables), _ptr(ccc),
                              _ptr(counts), ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_3way_rows")
     return tables, ccc, counts
 
 
-def _select(fn_name, width, v, n_f, threshold, cap, with_tables, counts, path, gamma, stream):
+def _select(fn_name, width, v, n_f, threshold, cap, with_tables, counts, path, gamma, stream,
+            operands="auto"):
     torch = _torch()
     _check_input(v)
     n_v, ld = v.shape
@@ -315,7 +321,7 @@ def _select(fn_name, width, v, n_f, threshold, cap, with_tables, counts, path, g
         counts = torch.empty((n_v, 4), dtype=torch.int32, device=dev)
     sel = ccc_selection(index.data_ptr(), cc.data_ptr(),
                         tables.data_ptr() if tables is not None else None, cap, count.data_ptr())
-    o = make_opts(path, gamma)
+    o = make_opts(path, gamma, operands=operands)
     st = getattr(lib(), fn_name)(_ptr(v), n_v, n_f, ld, float(threshold), ctypes.byref(sel),
                                  _ptr(counts), ctypes.byref(o), _stream(stream))
     _raise(st, fn_name)
@@ -325,23 +331,24 @@ def _select(fn_name, width, v, n_f, threshold, cap, with_tables, counts, path, g
 
 
 def ccc_2way_select(v, n_f, threshold, cap, with_tables=True, counts=None, path="auto",
-                    gamma=GAMMA, stream=None):
+                    gamma=GAMMA, stream=None, operands="auto"):
     """Pairs with some CCC value >= threshold: (number found, pair index [k], CCC [k, 4],
     tables [k, 4]) with k = min(found, cap), in unspecified order.  Synchronises to read
     the count."""
     return _select("ccc_2way_select", 4, v, n_f, threshold, cap, with_tables, counts, path,
-                   gamma, stream)
+                   gamma, stream, operands)
 
 
 def ccc_3way_select(v, n_f, threshold, cap, with_tables=True, counts=None, path="auto",
-                    gamma=GAMMA, stream=None):
+                    gamma=GAMMA, stream=None, operands="auto"):
     """Triples with some CCC value >= threshold (see ccc_2way_select)."""
     return _select("ccc_3way_select", 8, v, n_f, threshold, cap, with_tables, counts, path,
-                   gamma, stream)
+                   gamma, stream, operands)
 
 
 def ccc_2way_block(va, vb, n_f, tables, counts_a, counts_b, ccc=None, accumulate=False,
-                   finalize=True, path="auto", gamma=GAMMA, stream=None, field_offset=0):
+                   finalize=True, path="auto", gamma=GAMMA, stream=None, field_offset=0,
+                   operands="auto"):
     """Every (i in A, j in B) over one field chunk; tables/counts are the
     running state.  ``field_offset`` (bytes, a multiple of 16) selects the
     chunk inside wider rows: the chunk starts at byte ``field_offset`` of each
@@ -358,7 +365,7 @@ def ccc_2way_block(va, vb, n_f, tables, counts_a, counts_b, ccc=None, accumulate
     _check_out(counts_b, (n_b, 4), torch.int32, "counts_b")
     _check_out(ccc, (n_a, n_b, 4), torch.float64, "ccc")
     flags = (CCC_ACCUMULATE if accumulate else 0) | (CCC_FINALIZE if finalize else 0)
-    o = make_opts(path, gamma, flags)
+    o = make_opts(path, gamma, flags, operands)
     pa = ctypes.c_void_p(va.data_ptr() + field_offset)
     pb = ctypes.c_void_p(vb.data_ptr() + field_offset)
     st = lib().ccc_2way_block(pa, n_a, lda, pb, n_b, ldb, n_f, _ptr(tables), _ptr(counts_a),
@@ -367,7 +374,7 @@ def ccc_2way_block(va, vb, n_f, tables, counts_a, counts_b, ccc=None, accumulate
     return tables, ccc
 
 
-def ccc_2way_many(problems, path="auto", gamma=GAMMA, stream=None):
+def ccc_2way_many(problems, path="auto", gamma=GAMMA, stream=None, operands="auto"):
     """``problems``: sequence of dicts with keys v, n_f and optional tables,
     ccc, counts (outputs are allocated when absent).  Returns the list of
     (tables, ccc, counts)."""
@@ -395,7 +402,7 @@ def ccc_2way_many(problems, path="auto", gamma=GAMMA, stream=None):
                              t.data_ptr() if t is not None else None,
                              c.data_ptr() if c is not None else None, cnt.data_ptr())
         outs.append((t, c, cnt))
-    o = make_opts(path, gamma)
+    o = make_opts(path, gamma, operands=operands)
     st = lib().ccc_2way_many(arr, len(problems), ctypes.byref(o), _stream(stream))
     _raise(st, "ccc_2way_many")
     return outs

@@ -17,6 +17,9 @@
 namespace {
 
 constexpr int64_t kInt32Max = 2147483647;
+// Largest row stride: the kernels address a 16-row block of the input with
+// 32-bit byte offsets (15 ld + 64 < 2^32).
+constexpr int64_t kMaxLd = int64_t(1) << 28;
 // Largest row count whose complete-data Gram matrix (4 B per entry) the
 // 3-way MFMA path keeps in the workspace (4 GiB); beyond it every unit takes
 // the general path.
@@ -38,15 +41,32 @@ int resolve_opts(const ccc_opts* opts, ccc_opts* out) {
   if (opts->path < CCC_PATH_AUTO || opts->path > CCC_PATH_MFMA) return CCC_ERR_ARG;
   if (!isfinite(opts->gamma)) return CCC_ERR_ARG;
   if (opts->flags & ~(unsigned)(CCC_ACCUMULATE | CCC_FINALIZE)) return CCC_ERR_ARG;
+  if (opts->operands != CCC_OPERANDS_AUTO && opts->operands != CCC_OPERANDS_FP4 &&
+      opts->operands != CCC_OPERANDS_INT8)
+    return CCC_ERR_ARG;
+  if (opts->path == CCC_PATH_POPCOUNT && opts->operands != CCC_OPERANDS_AUTO) return CCC_ERR_ARG;
   *out = *opts;
   return CCC_OK;
 }
+
+// fp4 operands for an MFMA call whose largest per-call field count is n_f
+// (1), int8 (0), or CCC_ERR_RANGE when fp4 is forced beyond its exact range.
+int use_fp4(const ccc_opts& o, int64_t n_f) {
+  if (o.operands == CCC_OPERANDS_INT8) return 0;
+  if (o.operands == CCC_OPERANDS_FP4) return n_f <= ccc::kF4MaxFields ? 1 : CCC_ERR_RANGE;
+  return n_f <= ccc::kF4MaxFields ? 1 : 0;
+}
+
+// Table entries are at most 4 n_f (2-way) or 8 n_f (3-way): `mult` = 4 or 8.
+// Compared by division first, so that no product of a huge n_f overflows.
+bool fields_in_range(int64_t n_f, int64_t mult) { return n_f <= kInt32Max / mult; }
 
 int check_input(const uint8_t* v, int64_t n, int64_t n_f, int64_t ld) {
   if (n < 0 || n_f < 0 || ld < 0) return CCC_ERR_ARG;
   if (n > kInt32Max) return CCC_ERR_ARG;
   if (ld % 16 != 0) return CCC_ERR_ALIGN;
-  if (ld < (n_f + 3) / 4) return CCC_ERR_ARG;
+  if (ld > kMaxLd) return CCC_ERR_RANGE;
+  if (n_f / 4 >= ld + (n_f % 4 == 0)) return CCC_ERR_ARG;  // ld < ceil(n_f/4), overflow-free
   if (n > 0 && !v) return CCC_ERR_ARG;
   if (v && !aligned16(v)) return CCC_ERR_ALIGN;
   return CCC_OK;
@@ -96,10 +116,11 @@ ccc_opts ccc_default_opts(void) {
   o.path = CCC_PATH_AUTO;
   o.gamma = 2.0 / 3.0;
   o.flags = 0;
+  o.operands = CCC_OPERANDS_AUTO;
   return o;
 }
 
-int ccc_version(void) { return 100; }
+int ccc_version(void) { return 200; }
 
 int ccc_mfma_operands(int64_t n_f) {
   if (n_f < 0) return CCC_ERR_ARG;
@@ -132,7 +153,9 @@ int two_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_be
   if (st) return st;
   if (o.flags != 0) return CCC_ERR_ARG;
   if ((st = check_input(v, n_v, n_f, ld))) return st;
-  if (4 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  if (!fields_in_range(n_f, 4)) return CCC_ERR_RANGE;
+  const int f4 = o.path == CCC_PATH_POPCOUNT ? 0 : use_fp4(o, n_f);
+  if (f4 < 0) return f4;
   if (i_begin < 0 || i_end < i_begin || i_end > n_v) return CCC_ERR_ARG;
   if (sel) {
     if (!sel->index || !sel->ccc || !sel->count || sel->cap < 0) return CCC_ERR_ARG;
@@ -172,6 +195,7 @@ int two_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_be
   a.va = v; a.lda = ld; a.n_a = n_v;
   a.vb = v; a.ldb = ld; a.n_b = n_v;
   a.n_f = n_f;
+  a.f4 = f4;
   a.tri = 1;
   a.accumulate = 0;
   a.tables = tables;
@@ -201,7 +225,9 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   if (st) return st;
   if (o.flags != 0) return CCC_ERR_ARG;
   if ((st = check_input(v, n_v, n_f, ld))) return st;
-  if (8 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  if (!fields_in_range(n_f, 8)) return CCC_ERR_RANGE;
+  const int f4 = o.path == CCC_PATH_POPCOUNT ? 0 : use_fp4(o, n_f);
+  if (f4 < 0) return f4;
   if (i_begin < 0 || i_end < i_begin || i_end > n_v) return CCC_ERR_ARG;
   if (sel) {
     if (!sel->index || !sel->ccc || !sel->count || sel->cap < 0) return CCC_ERR_ARG;
@@ -240,6 +266,7 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   if (row_end <= i_begin) return CCC_OK;
   ccc::Triple3Args a{};
   a.v = v; a.ld = ld; a.n = n_v; a.n_f = n_f;
+  a.f4 = f4;
   a.tables = tables;
   a.ccc = ccc;
   a.counts = cnt;
@@ -313,7 +340,9 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   if (st) return st;
   if ((st = check_input(va, n_a, n_f, lda))) return st;
   if ((st = check_input(vb, n_b, n_f, ldb))) return st;
-  if (4 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  if (!fields_in_range(n_f, 4)) return CCC_ERR_RANGE;
+  const int f4 = o.path == CCC_PATH_POPCOUNT ? 0 : use_fp4(o, n_f);
+  if (f4 < 0) return f4;
   const bool acc = (o.flags & CCC_ACCUMULATE) != 0, fin = (o.flags & CCC_FINALIZE) != 0;
   if (n_a > 0 && n_b > 0) {
     if (!tables || !counts_a || !counts_b) return CCC_ERR_ARG;
@@ -342,6 +371,7 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   a.va = va; a.lda = lda; a.n_a = n_a;
   a.vb = vb; a.ldb = ldb; a.n_b = n_b;
   a.n_f = n_f;
+  a.f4 = f4;
   a.tri = 0;
   a.accumulate = acc ? 1 : 0;
   a.tables = tables;
@@ -369,11 +399,14 @@ int ccc_2way_multi(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s
   if (s < 2 || s > 4) return CCC_ERR_ARG;
   if (n_v < 0 || n_f < 0 || ld < 0 || n_v > kInt32Max) return CCC_ERR_ARG;
   if (ld % 16 != 0) return CCC_ERR_ALIGN;
+  if (ld > kMaxLd) return CCC_ERR_RANGE;
   if (ld < n_f) return CCC_ERR_ARG;
   if (n_v > 0 && !v) return CCC_ERR_ARG;
   if (!aligned16(v) || !aligned16(tables) || !aligned16(ccc) || !aligned16(counts))
     return CCC_ERR_ALIGN;
-  if (4 * n_f > kInt32Max) return CCC_ERR_RANGE;
+  if (!fields_in_range(n_f, 4)) return CCC_ERR_RANGE;
+  const int f4 = use_fp4(o, n_f);
+  if (f4 < 0) return f4;
   if (n_v >= 2 && !tables && !ccc) return CCC_ERR_ARG;
   if (n_v == 0 || (n_v == 1 && !counts)) return CCC_OK;
   int32_t* cnt = counts;
@@ -384,7 +417,8 @@ int ccc_2way_multi(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s
   }
   if (ccc::launch_multi_count(v, ld, n_v, n_f, s, cnt, stream) != hipSuccess) return CCC_ERR_HIP;
   if (n_v < 2) return CCC_OK;
-  return ccc::launch_multi2(v, ld, n_v, n_f, s, tables, ccc, cnt, o.gamma, stream) == hipSuccess
+  return ccc::launch_multi2(v, ld, n_v, n_f, s, tables, ccc, cnt, o.gamma, f4, stream) ==
+                 hipSuccess
              ? CCC_OK
              : CCC_ERR_HIP;
 }
@@ -396,15 +430,19 @@ int ccc_2way_many(const ccc_problem* probs, int n_probs, const ccc_opts* opts,
   if (st) return st;
   if (o.flags != 0) return CCC_ERR_ARG;
   if (n_probs < 0 || (n_probs > 0 && !probs)) return CCC_ERR_ARG;
+  int64_t nf_max = 0;
   for (int p = 0; p < n_probs; ++p) {
     const ccc_problem& q = probs[p];
     if ((st = check_input(q.v, q.n_v, q.n_f, q.ld))) return st;
-    if (4 * q.n_f > kInt32Max) return CCC_ERR_RANGE;
+    if (!fields_in_range(q.n_f, 4)) return CCC_ERR_RANGE;
+    if (q.n_f > nf_max) nf_max = q.n_f;
     if (q.n_v >= 2 && !q.tables && !q.ccc) return CCC_ERR_ARG;
     if (!aligned16(q.tables) || !aligned16(q.ccc) || !aligned16(q.counts)) return CCC_ERR_ALIGN;
   }
+  const int f4 = o.path == CCC_PATH_POPCOUNT ? 0 : use_fp4(o, nf_max);
+  if (f4 < 0) return f4;
   if (n_probs == 0) return CCC_OK;
-  return ccc::run_many(probs, n_probs, o, stream);
+  return ccc::run_many(probs, n_probs, o, f4 != 0, stream);
 }
 
 void ccc_release_workspace(void) {

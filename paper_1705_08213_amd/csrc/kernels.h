@@ -27,6 +27,7 @@ struct Pair2Args {
   const uint8_t* vb;
   int64_t ldb, n_b;
   int64_t n_f;
+  int f4;                     // MFMA operands: fp4 (1, needs n_f <= kF4MaxFields) or int8 (0)
   int tri;
   int accumulate;             // tables += result (rectangle only)
   int32_t* tables;            // may be null when ccc is set
@@ -45,7 +46,7 @@ struct Pair2Args {
   Select sel;                 // threshold selection (sel.count != null) instead of dense output
 };
 
-// Largest n_f for which the 2-way MFMA kernels take fp4 operands (their fp32
+// Largest n_f for which the MFMA kernels may take fp4 operands (their fp32
 // sums of quarter-multiples, at most n_f, stay exact); int8 beyond.
 constexpr int64_t kF4MaxFields = int64_t(1) << 22;
 
@@ -181,6 +182,7 @@ __host__ __device__ inline void strip_square(int64_t t, int64_t T, int64_t s0, i
 struct Triple3Args {
   const uint8_t* v;
   int64_t ld, n, n_f;
+  int f4;         // MFMA operands: fp4 (1, needs n_f <= kF4MaxFields) or int8 (0)
   int32_t* tables;
   double* ccc;
   const int32_t* counts;
@@ -202,6 +204,8 @@ enum Path { kPathPopcount = 1, kPathMfma = 2 };
 // enabled through ccc_timing_enable).
 void timing_begin(const char* name, hipStream_t stream);
 void timing_end(hipStream_t stream);
+// A host-side duration under `name` (recorded only while timing is enabled).
+void timing_host(const char* name, double ms);
 
 hipError_t launch_count1(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int32_t* counts,
                          int accumulate, hipStream_t stream);
@@ -219,6 +223,6 @@ hipError_t launch_multi_count(const uint8_t* v, int64_t ld, int64_t n, int64_t n
                               int32_t* counts, hipStream_t stream);
 hipError_t launch_multi2(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int s,
                          int32_t* tables, double* ccc, const int32_t* counts, double gamma,
-                         hipStream_t stream);
+                         int f4, hipStream_t stream);
 
 }  // namespace ccc

@@ -29,6 +29,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -85,6 +86,7 @@ __device__ __forceinline__ Pair2Args pair_args(const ProbDesc& p, double gamma) 
   a.va = p.v; a.lda = p.ld; a.n_a = p.n_v;
   a.vb = p.v; a.ldb = p.ld; a.n_b = p.n_v;
   a.n_f = p.n_f;
+  a.f4 = 0;  // the operand format is the kernel's template argument
   a.tri = 1;
   a.accumulate = 0;
   a.tables = p.tables;
@@ -233,7 +235,7 @@ struct Entry {
   int item_begin[kVariants] = {0, 0}, n_items[kVariants] = {0, 0};
   int64_t total_rows = 0;
   int path = 0;
-  bool f4 = true;                 // fp4 operands (all n_f <= kF4MaxFields)
+  bool f4 = true;                 // fp4 operands (every n_f <= kF4MaxFields), else int8
   double gamma = 0;
   int grid[kVariants] = {0, 0};
   hipStream_t fork = nullptr;     // second capture stream for a concurrent variant
@@ -255,7 +257,8 @@ void destroy(Entry* e) {
   delete e;
 }
 
-std::vector<unsigned char> make_key(const ccc_problem* probs, int n, const ccc_opts& o) {
+std::vector<unsigned char> make_key(const ccc_problem* probs, int n, const ccc_opts& o,
+                                    bool f4) {
   std::vector<unsigned char> k(sizeof(ccc_problem) * n + sizeof(int) + sizeof(double) + 64);
   size_t off = 0;
   memcpy(k.data(), probs, sizeof(ccc_problem) * n);
@@ -272,6 +275,9 @@ std::vector<unsigned char> make_key(const ccc_problem* probs, int n, const ccc_o
   const char* env = getenv("CCC_MANY_VARIANT");
   int forced = env ? atoi(env) + 1 : 0;
   memcpy(k.data() + off, &forced, sizeof(int));
+  off += sizeof(int);
+  const int operands = f4 ? 4 : 8;
+  memcpy(k.data() + off, &operands, sizeof(int));
   off += sizeof(int);
   k.resize(off);
   return k;
@@ -320,7 +326,8 @@ hipError_t enqueue(const Entry& e, hipStream_t stream, bool fork) {
 }
 
 // Build descriptors and the LPT-ordered work list; allocate and upload.
-int build_entry(const ccc_problem* probs, int n, const ccc_opts& o, Entry* e) {
+int build_entry(const ccc_problem* probs, int n, const ccc_opts& o, bool f4, Entry* e) {
+  e->f4 = f4;
   std::vector<ProbDesc> d(n);
   std::vector<WorkItem> items[kVariants];
   std::vector<int64_t> cost[kVariants];
@@ -336,7 +343,6 @@ int build_entry(const ccc_problem* probs, int n, const ccc_opts& o, Entry* e) {
     x.ccc = q.ccc;
     x.counts = q.counts;
     x.row_begin = rows;
-    if (q.n_f > kF4MaxFields) e->f4 = false;
     x.variant = o.path == CCC_PATH_POPCOUNT ? 0 : pick_variant(q.n_v, q.n_f, CCC_PATH_MFMA);
     const int side = o.path == CCC_PATH_POPCOUNT ? kPopTile : kSquare[x.variant];
     const int64_t T = (q.n_v + side - 1) / side;
@@ -408,11 +414,12 @@ bool graphs_enabled() {
 
 }  // namespace
 
-int run_many(const ccc_problem* probs, int n_probs, const ccc_opts& opts, hipStream_t stream) {
+int run_many(const ccc_problem* probs, int n_probs, const ccc_opts& opts, bool f4,
+             hipStream_t stream) {
   int64_t rows = 0;
   for (int p = 0; p < n_probs; ++p) rows += probs[p].n_v;
   if (rows == 0) return CCC_OK;
-  std::vector<unsigned char> key = make_key(probs, n_probs, opts);
+  std::vector<unsigned char> key = make_key(probs, n_probs, opts, f4);
   std::lock_guard<std::mutex> lk(g_mu);
   Entry* e = nullptr;
   for (Entry* c : g_cache)
@@ -426,9 +433,10 @@ int run_many(const ccc_problem* probs, int n_probs, const ccc_opts& opts, hipStr
       destroy(*oldest);
       g_cache.erase(oldest);
     }
+    const auto t0 = std::chrono::steady_clock::now();
     e = new Entry();
     e->key = key;
-    int st = build_entry(probs, n_probs, opts, e);
+    int st = build_entry(probs, n_probs, opts, f4, e);
     if (st != CCC_OK) {
       destroy(e);
       return st;
@@ -453,6 +461,8 @@ int run_many(const ccc_problem* probs, int n_probs, const ccc_opts& opts, hipStr
       }
     }
     g_cache.push_back(e);
+    timing_host("many_setup", std::chrono::duration<double, std::milli>(
+                                  std::chrono::steady_clock::now() - t0).count());
   }
   e->last_use = ++g_clock;
   timing_begin("many", stream);

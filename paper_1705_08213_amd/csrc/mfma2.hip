@@ -1,6 +1,6 @@
-// mfma2.hip -- 2-way tallies on the int8 matrix cores: the one-shot kernel
-// over the triangle (ccc_2way) or the rectangle (ccc_2way_block).  The tile
-// body and its design notes are in tile2.h.
+// mfma2.hip -- 2-way tallies on the matrix cores (fp4 or int8 operands): the
+// one-shot kernel over the triangle (ccc_2way) or the rectangle
+// (ccc_2way_block).  The tile body and its design notes are in tile2.h.
 #include "tile2.h"
 
 namespace ccc {
@@ -52,7 +52,7 @@ hipError_t launch_shape(const Pair2Args& a, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   timing_begin("mfma2", stream);
-  if (a.n_f <= kF4MaxFields)
+  if (a.f4)
     hipLaunchKernelGGL((mfma2_kernel<WM, WN, true>), dim3((unsigned)ntiles), dim3(256), 0, stream,
                        b, tm, tn);
   else

@@ -742,7 +742,7 @@ hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (a.n_f <= kF4MaxFields) return launch_units(mfma3_kernel<true>, a, BI, "mfma3", stream);
+  if (a.f4) return launch_units(mfma3_kernel<true>, a, BI, "mfma3", stream);
   return launch_units(mfma3_kernel<false>, a, BI, "mfma3", stream);
 }
 

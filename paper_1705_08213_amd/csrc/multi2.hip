@@ -439,9 +439,8 @@ hipError_t launch_multi2_shape(const Multi2Args& a, hipStream_t stream) {
 }
 
 template <int S>
-hipError_t launch_multi2_s(const Multi2Args& a, hipStream_t stream) {
-  return a.n_f <= kF4MaxFields ? launch_multi2_shape<S, true>(a, stream)
-                               : launch_multi2_shape<S, false>(a, stream);
+hipError_t launch_multi2_s(const Multi2Args& a, int f4, hipStream_t stream) {
+  return f4 ? launch_multi2_shape<S, true>(a, stream) : launch_multi2_shape<S, false>(a, stream);
 }
 
 }  // namespace
@@ -456,12 +455,12 @@ hipError_t launch_multi_count(const uint8_t* v, int64_t ld, int64_t n, int64_t n
 
 hipError_t launch_multi2(const uint8_t* v, int64_t ld, int64_t n, int64_t n_f, int s,
                          int32_t* tables, double* ccc, const int32_t* counts, double gamma,
-                         hipStream_t stream) {
+                         int f4, hipStream_t stream) {
   Multi2Args a{v, ld, n, n_f, tables, ccc, counts, gamma};
   switch (s) {
-    case 2: return launch_multi2_s<2>(a, stream);
-    case 3: return launch_multi2_s<3>(a, stream);
-    case 4: return launch_multi2_s<4>(a, stream);
+    case 2: return launch_multi2_s<2>(a, f4, stream);
+    case 3: return launch_multi2_s<3>(a, f4, stream);
+    case 4: return launch_multi2_s<4>(a, f4, stream);
     default: return hipErrorInvalidValue;
   }
 }

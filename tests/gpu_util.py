@@ -55,3 +55,17 @@ def assert_tables_equal(got: np.ndarray, want: np.ndarray):
         bad = np.argwhere(got != want)[:5]
         raise AssertionError(f"{int((got != want).sum())} table entries differ, first at "
                              f"{bad.tolist()}: got {got[tuple(bad.T)]} want {want[tuple(bad.T)]}")
+
+
+# The computation forms the parity tests run: the popcount path and the MFMA
+# path with each operand format forced (fp4 and int8 both run on multi-tile
+# problems, whatever size would pick by default).
+FORMS = ["popcount", "fp4", "int8"]
+MFMA_FORMS = ["fp4", "int8"]
+
+
+def form_kw(form: str) -> dict:
+    """Keyword arguments of a binding call for one of FORMS."""
+    if form == "popcount":
+        return dict(path="popcount")
+    return dict(path="mfma", operands=form)

@@ -25,7 +25,7 @@ def test_status_strings_and_version():
         s = ccc.status_string(st)
         assert s and s != "unknown status"
     assert ccc.status_string(-99) == "unknown status"
-    assert ccc.version() >= 100
+    assert ccc.version() >= 200
 
 
 def test_two_way_operand_format_query():
@@ -41,6 +41,70 @@ def test_default_opts():
     o = ccc.lib().ccc_default_opts()
     assert o.path == ccc.CCC_PATH_AUTO and o.flags == 0
     assert o.gamma == 2.0 / 3.0
+    assert o.operands == ccc.CCC_OPERANDS_AUTO
+
+
+@pytest.mark.parametrize("fn", ["2way", "3way", "block", "multi", "many"])
+def test_operand_format_option(fn):
+    """Unknown formats and a format with the popcount path are argument
+    errors; fp4 forced past 2^22 fields (where its fp32 sums stop being exact)
+    is a range error.  All are caught before any device work."""
+    L = ccc.lib()
+    limit = 1 << 22
+
+    def call(n_f, path="mfma", operands="auto"):
+        o = ccc.make_opts(path, operands=operands)
+        ld = (n_f + 3) // 4 // 16 * 16 + 16
+        if fn == "2way":
+            return L.ccc_2way(FAKE, 10, n_f, ld, FAKE, FAKE, None, ctypes.byref(o), None)
+        if fn == "3way":
+            return L.ccc_3way(FAKE, 10, n_f, ld, FAKE, FAKE, None, ctypes.byref(o), None)
+        if fn == "block":
+            o.flags = ccc.CCC_FINALIZE
+            return L.ccc_2way_block(FAKE, 8, ld, FAKE, 9, ld, n_f, FAKE, FAKE, FAKE, FAKE,
+                                    ctypes.byref(o), None)
+        if fn == "multi":
+            ldm = (n_f + 15) // 16 * 16
+            return L.ccc_2way_multi(FAKE, 10, n_f, ldm, 3, FAKE, FAKE, None, ctypes.byref(o),
+                                    None)
+        P = ccc.ccc_problem
+        arr = (P * 2)(P(FAKE, 10, 100, 32, FAKE, FAKE, FAKE),
+                      P(FAKE, 10, n_f, ld, FAKE, FAKE, FAKE))
+        return L.ccc_2way_many(arr, 2, ctypes.byref(o), None)
+
+    assert call(100, operands=3) == ccc.CCC_ERR_ARG
+    assert call(100, operands=-4) == ccc.CCC_ERR_ARG
+    assert call(limit + 1, operands="fp4") == ccc.CCC_ERR_RANGE
+    assert call(limit + 257, operands="fp4") == ccc.CCC_ERR_RANGE
+    if fn != "multi":  # multi-allelic tallies have no popcount form
+        assert call(100, path="popcount", operands="int8") == ccc.CCC_ERR_ARG
+        assert call(100, path="popcount", operands="fp4") == ccc.CCC_ERR_ARG
+
+
+def test_row_stride_and_field_count_limits():
+    """ld beyond 2^28 bytes (the kernels' 32-bit block offsets) is a range
+    error; so is any n_f whose table entries could pass INT32_MAX, even one so
+    large that 4 n_f or 8 n_f would overflow int64."""
+    big_ld = (1 << 28) + 16
+    assert call2(ld=big_ld) == ccc.CCC_ERR_RANGE
+    assert call3(ld=big_ld) == ccc.CCC_ERR_RANGE
+    assert callb(lda=big_ld) == ccc.CCC_ERR_RANGE
+    assert callb(ldb=big_ld) == ccc.CCC_ERR_RANGE
+    assert call2(ld=1 << 28, n_f=4 << 28) == ccc.CCC_ERR_RANGE  # 4 n_f = 2^32
+    for huge in ((1 << 62) + 1, (1 << 63) - 1, 1 << 61):
+        # ld cannot hold such rows: the stride check fires before any product of n_f
+        assert call2(n_f=huge, ld=1 << 28) == ccc.CCC_ERR_ARG
+        assert call3(n_f=huge, ld=1 << 28) == ccc.CCC_ERR_ARG
+    L = ccc.lib()
+    o = ccc.make_opts()
+    assert L.ccc_2way_multi(FAKE, 10, 100, big_ld, 3, FAKE, FAKE, None, ctypes.byref(o),
+                            None) == ccc.CCC_ERR_RANGE
+    assert L.ccc_2way_multi(FAKE, 10, (1 << 62) + 1, 1 << 28, 3, FAKE, FAKE, None,
+                            ctypes.byref(o), None) == ccc.CCC_ERR_ARG
+    P = ccc.ccc_problem
+    arr = (P * 2)(P(FAKE, 10, 100, 32, FAKE, FAKE, FAKE),
+                  P(FAKE, 10, 100, big_ld, FAKE, FAKE, FAKE))
+    assert L.ccc_2way_many(arr, 2, None, None) == ccc.CCC_ERR_RANGE
 
 
 def call2(v=FAKE, n_v=10, n_f=100, ld=32, tables=FAKE, cc=FAKE, counts=None, opts=None):

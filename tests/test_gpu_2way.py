@@ -1,5 +1,6 @@
-"""2-way parity on the GPU: both HIP paths (popcount, int8 MFMA) against the
-CPU oracle, element by element, bit-exact tables and CCC within 1e-12."""
+"""2-way parity on the GPU: the popcount path and the MFMA path with fp4 and
+with int8 operands, against the CPU oracle, element by element: bit-exact
+tables and CCC within 1e-12."""
 import numpy as np
 import pytest
 
@@ -7,12 +8,12 @@ import oracle
 import oracle.brute
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import (assert_ccc_close, assert_ccc_identical, assert_tables_equal, dev, host,
-                      say)
+from gpu_util import (FORMS, assert_ccc_close, assert_ccc_identical, assert_tables_equal, dev,
+                      form_kw, host, say)
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["popcount", "mfma"]
+PATHS = FORMS
 
 # (n_v, n_f, missing, extra ld units): tiny, ragged in both dimensions, several
 # tiles and super-steps, tails of every length class
@@ -24,7 +25,7 @@ SHAPES = [
 
 
 def run2(v, n_f, path, **kw):
-    t, c, cnt = ccc.ccc_2way(dev(v), n_f, path=path, **kw)
+    t, c, cnt = ccc.ccc_2way(dev(v), n_f, **form_kw(path), **kw)
     import torch
     torch.cuda.synchronize()
     return (None if t is None else host(t)), (None if c is None else host(c)), host(cnt)
@@ -98,12 +99,14 @@ def test_2way_outputs_optional_and_gamma(path):
 def test_2way_paths_agree_and_are_deterministic():
     say("2way cross-path")
     v = synth.beta_hw(1000, 5003, seed=9, missing=0.01)
-    tm, cm, _ = run2(v, 5003, "mfma")
+    tm, cm, _ = run2(v, 5003, "fp4")
     tp, cp, _ = run2(v, 5003, "popcount")
-    tm2, cm2, _ = run2(v, 5003, "mfma")
-    assert np.array_equal(tm, tp) and np.array_equal(tm, tm2)
+    ti, ci, _ = run2(v, 5003, "int8")
+    tm2, cm2, _ = run2(v, 5003, "fp4")
+    assert np.array_equal(tm, tp) and np.array_equal(tm, tm2) and np.array_equal(tm, ti)
     assert np.array_equal(cm, cm2)
     assert_ccc_close(cm, cp, rtol=0.0)
+    assert_ccc_close(cm, ci, rtol=0.0)
     # sampled rows against the oracle
     for i0, i1 in [(0, 2), (511, 513), (997, 999)]:
         ot, oc = oracle.two_way(v, 5003, i0, i1)

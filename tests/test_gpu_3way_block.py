@@ -6,12 +6,12 @@ import oracle
 import oracle.brute
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import (assert_ccc_close, assert_ccc_identical, assert_tables_equal, dev, host,
-                      say)
+from gpu_util import (FORMS, MFMA_FORMS, assert_ccc_close, assert_ccc_identical,
+                      assert_tables_equal, dev, form_kw, host, say)
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["popcount", "mfma"]
+PATHS = FORMS
 
 SHAPES3 = [(3, 1, 0.0), (4, 7, 0.2), (9, 100, 0.05), (33, 257, 0.01), (66, 300, 0.01),
            (70, 1000, 0.005), (130, 129, 0.02), (150, 2050, 0.005)]
@@ -27,7 +27,7 @@ def sync():
 def test_3way_parity(path, n_v, n_f, missing):
     say("3way", path, n_v, n_f, missing)
     v = synth.beta_hw(n_v, n_f, seed=n_v + 13 * n_f, missing=missing)
-    t, c, cnt = ccc.ccc_3way(dev(v), n_f, path=path)
+    t, c, cnt = ccc.ccc_3way(dev(v), n_f, **form_kw(path))
     sync()
     ot, oc = oracle.three_way(v, n_f)
     assert_tables_equal(host(t), ot)
@@ -39,14 +39,14 @@ def test_3way_parity(path, n_v, n_f, missing):
 def test_3way_closed_form_and_zero_fields(path):
     say("3way closed", path)
     v = synth.constant([1, 1, 1, 2, 0], 515)
-    t, c, _ = ccc.ccc_3way(dev(v), 515, path=path)
+    t, c, _ = ccc.ccc_3way(dev(v), 515, **form_kw(path))
     sync()
     t, c = host(t), host(c)
     p = oracle.triple_index(5, 0, 1, 2)
     assert list(t[p]) == [515] * 8
     assert np.all(np.abs(c[p] - 1 / 27) <= 1e-15)
     v0 = synth.uniform(20, 0)
-    t0, c0, _ = ccc.ccc_3way(dev(v0), 0, path=path)
+    t0, c0, _ = ccc.ccc_3way(dev(v0), 0, **form_kw(path))
     sync()
     assert np.all(host(t0) == 0) and np.all(host(c0) == 0.0)
 
@@ -59,7 +59,7 @@ def test_3way_complete_data_and_single_missing_entry(path, n_v, n_f):
     sends only the units that hold its row (as i, j or k) to the general form."""
     say("3way complete", path, n_v, n_f)
     v = synth.beta_hw(n_v, n_f, seed=300 + n_v, missing=0.0)
-    t, c, _ = ccc.ccc_3way(dev(v), n_f, path=path)
+    t, c, _ = ccc.ccc_3way(dev(v), n_f, **form_kw(path))
     sync()
     ot, oc = oracle.three_way(v, n_f)
     assert_tables_equal(host(t), ot)
@@ -67,26 +67,27 @@ def test_3way_complete_data_and_single_missing_entry(path, n_v, n_f):
     codes = oracle.brute.unpack_codes(v, n_f)
     codes[n_v // 2, n_f // 3] = 2  # one missing entry
     v2 = synth.pack_codes(codes, pad_value=-1)
-    t2, c2, _ = ccc.ccc_3way(dev(v2), n_f, path=path)
+    t2, c2, _ = ccc.ccc_3way(dev(v2), n_f, **form_kw(path))
     sync()
     ot2, oc2 = oracle.three_way(v2, n_f)
     assert_tables_equal(host(t2), ot2)
     assert_ccc_close(host(c2), oc2)
 
 
-def test_3way_complete_data_rows_and_select():
+@pytest.mark.parametrize("form", MFMA_FORMS)
+def test_3way_complete_data_rows_and_select(form):
     """Row ranges whose first row is not on a 64-row unit boundary (the pair
     sums then start at the unit boundary below it) and threshold selection,
     on complete data."""
     import torch
     n, n_f = 150, 777
-    say("3way complete rows/select")
+    say("3way complete rows/select", form)
     v = synth.beta_hw(n, n_f, seed=905, missing=0.0)
     dv = dev(v)
-    t_full, c_full, _ = ccc.ccc_3way(dv, n_f, path="mfma")
+    t_full, c_full, _ = ccc.ccc_3way(dv, n_f, **form_kw(form))
     parts = []
     for i0, i1 in [(0, 5), (5, 64), (64, 70), (70, 129), (129, 150)]:
-        t, c, _ = ccc.ccc_3way_rows(dv, n_f, i0, i1, path="mfma")
+        t, c, _ = ccc.ccc_3way_rows(dv, n_f, i0, i1, **form_kw(form))
         sync()
         ot, oc = oracle.three_way(v, n_f, i0, i1)
         assert_tables_equal(host(t), ot)
@@ -100,7 +101,7 @@ def test_3way_complete_data_rows_and_select():
     u = np.unique(mx)
     thr = 0.5 * (u[-51] + u[-50])
     want = np.flatnonzero(mx >= thr)
-    found, idx, cc, tt = ccc.ccc_3way_select(dv, n_f, thr, cap=len(want), path="mfma")
+    found, idx, cc, tt = ccc.ccc_3way_select(dv, n_f, thr, cap=len(want), **form_kw(form))
     assert found == len(want)
     idx, cc, tt = host(idx), host(cc), host(tt)
     order = np.argsort(idx)
@@ -115,7 +116,7 @@ def test_3way_ccc_bit_identical_to_oracle(path, missing):
     """Beyond the 1e-12 contract: every CCC double equals the oracle's."""
     say("3way bit-identical", path, missing)
     v = synth.beta_hw(100, 1500, seed=42, missing=missing)
-    _, c, _ = ccc.ccc_3way(dev(v), 1500, path=path)
+    _, c, _ = ccc.ccc_3way(dev(v), 1500, **form_kw(path))
     sync()
     _, oc = oracle.three_way(v, 1500)
     assert_ccc_identical(host(c), oc)
@@ -124,11 +125,12 @@ def test_3way_ccc_bit_identical_to_oracle(path, missing):
 def test_3way_paths_agree():
     say("3way cross-path")
     v = synth.beta_hw(200, 3000, seed=21, missing=0.005)
-    tm, cm, _ = ccc.ccc_3way(dev(v), 3000, path="mfma")
+    tm, cm, _ = ccc.ccc_3way(dev(v), 3000, **form_kw("fp4"))
     tp, cp, _ = ccc.ccc_3way(dev(v), 3000, path="popcount")
+    ti, ci, _ = ccc.ccc_3way(dev(v), 3000, **form_kw("int8"))
     sync()
-    assert np.array_equal(host(tm), host(tp))
-    assert np.array_equal(host(cm), host(cp))
+    assert np.array_equal(host(tm), host(tp)) and np.array_equal(host(tm), host(ti))
+    assert np.array_equal(host(cm), host(cp)) and np.array_equal(host(cm), host(ci))
     ot, oc = oracle.three_way(v, 3000, 100, 102)
     lo = oracle.triple_index(200, 100, 101, 102)
     assert_tables_equal(host(tm)[lo:lo + len(ot)], ot)
@@ -149,7 +151,7 @@ def test_block_one_shot(path, n_a, n_b, n_f, missing):
     ca = torch.empty((n_a, 4), dtype=torch.int32, device="cuda")
     cb = torch.empty((n_b, 4), dtype=torch.int32, device="cuda")
     cc = torch.empty((n_a, n_b, 4), dtype=torch.float64, device="cuda")
-    ccc.ccc_2way_block(dev(va), dev(vb), n_f, tables, ca, cb, cc, path=path)
+    ccc.ccc_2way_block(dev(va), dev(vb), n_f, tables, ca, cb, cc, **form_kw(path))
     sync()
     ot, oc = oracle.block(va, vb, n_f)
     assert_tables_equal(host(tables), ot)
@@ -174,7 +176,7 @@ def test_block_complete_data_and_one_missing_entry(path):
         ca = torch.empty((n_a, 4), dtype=torch.int32, device="cuda")
         cb = torch.empty((n_b, 4), dtype=torch.int32, device="cuda")
         cc = torch.empty((n_a, n_b, 4), dtype=torch.float64, device="cuda")
-        ccc.ccc_2way_block(dev(va), dev(b), n_f, tables, ca, cb, cc, path=path)
+        ccc.ccc_2way_block(dev(va), dev(b), n_f, tables, ca, cb, cc, **form_kw(path))
         sync()
         ot, oc = oracle.block(va, b, n_f)
         assert_tables_equal(host(tables), ot)
@@ -198,7 +200,7 @@ def test_block_chunked_equals_one_shot(path):
     for k in range(nchunks + 1):
         nf_k = chunk if k < nchunks else last
         ccc.ccc_2way_block(da, db, nf_k, tables, ca, cb, cc, accumulate=k > 0,
-                           finalize=k == nchunks, path=path, field_offset=k * chunk // 4)
+                           finalize=k == nchunks, field_offset=k * chunk // 4, **form_kw(path))
     sync()
     ot, oc = oracle.block(va, vb, n_f)
     assert_tables_equal(host(tables), ot)

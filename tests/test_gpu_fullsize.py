@@ -2,7 +2,9 @@
 times: every table through a whole-output checksum (weighted sums mod 2^61-1
 that the oracle evaluates from the input in O(n_v n_f)), sampled pairs and
 triples against the oracle one by one (tables bit-exact, CCC within 1e-12),
-the 1-way counts in full, and the two HIP paths against each other."""
+the 1-way counts in full, and the HIP forms against each other: popcount,
+and the MFMA path with fp4 and with int8 operands (forced; fp4 is what the
+default picks at these sizes)."""
 import numpy as np
 import pytest
 
@@ -67,7 +69,13 @@ def test_c2_2way_large_full_size():
     p = pair_index_np(n_v, ia, jb)
     assert_tables_equal(gather_rows(t, p), ot)
     assert_ccc_close(gather_rows(c, p), oc)
-    del c
+    say("c2 full size: int8 ccc_2way")
+    ti, ci, _ = ccc.ccc_2way(dv, n_f, path="mfma", operands="int8")
+    sync()
+    assert_tables_equal(gather_rows(ti, p), ot)
+    assert_ccc_close(gather_rows(ci, p), oc)
+    assert torch.equal(t, ti) and torch.equal(c, ci)
+    del c, ti, ci
     say("c2 full size: popcount ccc_2way")
     tp, _, _ = ccc.ccc_2way(dv, n_f, path="popcount", want_ccc=False)
     sync()
@@ -108,6 +116,22 @@ def test_c3_3way_full_size():
     p = [oracle.triple_index(n_v, int(a), int(b), int(d)) for a, b, d in zip(ii, jj, kk)]
     assert_tables_equal(gather_rows(t, p), ot)
     assert_ccc_close(gather_rows(c, p), oc)
+    # int8 operands: every table (45.7 GB beside the fp4 output), and the CCC
+    # values of two staged row runs
+    say("c3 full size: int8 ccc_3way tables")
+    ti, _, _ = ccc.ccc_3way(dv, n_f, path="mfma", operands="int8", want_ccc=False)
+    sync()
+    assert_tables_equal(gather_rows(ti, p), ot)
+    assert torch.equal(t, ti)
+    del ti
+    for i0, i1 in [(0, 3), (1000, 1066)]:
+        say("c3 full size: int8 ccc_3way_rows", i0, i1)
+        tr, cr, _ = ccc.ccc_3way_rows(dv, n_f, i0, i1, path="mfma", operands="int8")
+        sync()
+        lo = oracle.triple_index(n_v, i0, i0 + 1, i0 + 2)
+        assert torch.equal(tr, t[lo:lo + tr.shape[0]])
+        assert torch.equal(cr, c[lo:lo + cr.shape[0]])
+        del tr, cr
     del c
     say("c3 full size: checksum over slices")
     w, u, z = (synth.weights(n_v, seed=6, tag=k) for k in range(3))
@@ -125,6 +149,7 @@ def test_c3_shape_complete_data_full_size():
     """The 3-way shape with no missing entries: every unit takes the one-plane
     complete-data form.  Sampled triples against the oracle one by one, every
     table through the whole-output checksum."""
+    import torch
     n_v, n_f = 2048, 16384
     say("c3 complete: generate")
     v = synth.beta_hw(n_v, n_f, seed=0, missing=0.0)
@@ -148,6 +173,12 @@ def test_c3_shape_complete_data_full_size():
     assert_tables_equal(gather_rows(t, p), ot)
     assert_ccc_close(gather_rows(c, p), oc)
     del c
+    say("c3 complete: int8 ccc_3way tables")
+    ti, _, _ = ccc.ccc_3way(dv, n_f, path="mfma", operands="int8", want_ccc=False)
+    sync()
+    assert_tables_equal(gather_rows(ti, p), ot)
+    assert torch.equal(t, ti)
+    del ti
     say("c3 complete: checksum over slices")
     w, u, z = (synth.weights(n_v, seed=14, tag=k) for k in range(3))
     total = np.zeros(8, dtype=np.uint64)
@@ -176,6 +207,17 @@ def test_c5_block_full_size_chunked():
         ccc.ccc_2way_block(da, db, chunk, tables, ca, cb, cc, accumulate=k > 0,
                            finalize=k == n_f // chunk - 1, field_offset=k * chunk // 4)
     sync()
+    say("c5 full size: 8 chunk calls, int8 operands")
+    ti, ci = torch.empty_like(tables), torch.empty_like(cc)
+    cai, cbi = torch.empty_like(ca), torch.empty_like(cb)
+    for k in range(n_f // chunk):
+        ccc.ccc_2way_block(da, db, chunk, ti, cai, cbi, ci, accumulate=k > 0,
+                           finalize=k == n_f // chunk - 1, field_offset=k * chunk // 4,
+                           path="mfma", operands="int8")
+    sync()
+    assert torch.equal(ti, tables) and torch.equal(ci, cc)
+    assert torch.equal(cai, ca) and torch.equal(cbi, cb)
+    del ti, ci
     assert np.array_equal(ca.cpu().numpy()[:, :3], oracle.counts1(va, n_f))
     assert np.array_equal(cb.cpu().numpy()[:, :3], oracle.counts1(vb, n_f))
     rng = np.random.default_rng(4)
@@ -220,6 +262,13 @@ def test_c4_batched_full_size():
         w, u = synth.weights(n_v, seed=8, tag=0), synth.weights(n_v, seed=8, tag=1)
         assert np.array_equal(oracle.fp2_from_tables(t.cpu().numpy(), n_v, w, u),
                               oracle.fp2_from_input(v, n_f, w, u)), k
+    say("c4 full size: ccc_2way_many, int8 operands")
+    outs_i = ccc.ccc_2way_many([dict(v=p["v"], n_f=p["n_f"]) for p in probs], path="mfma",
+                               operands="int8")
+    sync()
+    for k in range(64):
+        assert all(torch.equal(x, y) for x, y in zip(outs[k], outs_i[k])), k
+    del outs_i
     # the batch equals independent calls
     say("c4 full size: against single calls")
     for k in (0, 17, 63):
@@ -246,7 +295,11 @@ def test_c2_shape_complete_data_full_size():
     p = pair_index_np(n_v, ia, jb)
     assert_tables_equal(gather_rows(t, p), ot)
     assert_ccc_close(gather_rows(c, p), oc)
-    del c
+    say("c2 complete: int8 operands")
+    ti, ci, _ = ccc.ccc_2way(dv, n_f, path="mfma", operands="int8")
+    sync()
+    assert torch.equal(t, ti) and torch.equal(c, ci)
+    del c, ti, ci
     say("c2 complete: checksum")
     w, u = synth.weights(n_v, seed=9, tag=0), synth.weights(n_v, seed=9, tag=1)
     assert np.array_equal(oracle.fp2_from_tables(t.cpu().numpy(), n_v, w, u),

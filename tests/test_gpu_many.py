@@ -10,7 +10,7 @@ import pytest
 import oracle
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import assert_ccc_close, assert_tables_equal, dev, host, say
+from gpu_util import FORMS, MFMA_FORMS, assert_ccc_close, assert_tables_equal, dev, form_kw, host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -42,11 +42,11 @@ def variant(request, monkeypatch):
     yield request.param
 
 
-@pytest.mark.parametrize("path", ["mfma", "popcount"])
+@pytest.mark.parametrize("path", FORMS)
 def test_many_matches_oracle(variant, path):
     say("many", variant, path)
     hosts, probs = make_batch(SIZES, seed=500)
-    outs = ccc.ccc_2way_many(probs, path=path)
+    outs = ccc.ccc_2way_many(probs, **form_kw(path))
     sync()
     for (n_v, n_f), v, (t, c, cnt) in zip(SIZES, hosts, outs):
         ot, oc = oracle.two_way(v, n_f)
@@ -55,13 +55,13 @@ def test_many_matches_oracle(variant, path):
         assert np.array_equal(host(cnt)[:, :3], oracle.counts1(v, n_f))
 
 
-@pytest.mark.parametrize("path", ["mfma", "popcount"])
+@pytest.mark.parametrize("path", FORMS)
 def test_many_complete_data_problems(variant, path):
     """A batch with no missing entries: the persistent kernels take the
     per-wave (MFMA) or per-workgroup (popcount) complete-data form."""
     say("many complete", variant, path)
     hosts, probs = make_batch(SIZES, seed=700, missing=0.0)
-    outs = ccc.ccc_2way_many(probs, path=path)
+    outs = ccc.ccc_2way_many(probs, **form_kw(path))
     sync()
     for (n_v, n_f), v, (t, c, _) in zip(SIZES, hosts, outs):
         ot, oc = oracle.two_way(v, n_f)
@@ -69,11 +69,12 @@ def test_many_complete_data_problems(variant, path):
         assert_ccc_close(host(c), oc)
 
 
-def test_many_graph_replays_with_eager_work_between(variant):
+@pytest.mark.parametrize("form", MFMA_FORMS)
+def test_many_graph_replays_with_eager_work_between(variant, form):
     import torch
-    say("many replays", variant)
+    say("many replays", variant, form)
     hosts, probs = make_batch(SIZES[:6] + [(2000, 3000)], seed=600)
-    outs = ccc.ccc_2way_many(probs)
+    outs = ccc.ccc_2way_many(probs, **form_kw(form))
     sync()
     ref = [(t.clone(), c.clone(), cnt.clone()) for t, c, cnt in outs]
     for p, (t, c, cnt) in zip(probs, outs):
@@ -85,7 +86,7 @@ def test_many_graph_replays_with_eager_work_between(variant):
             cnt.fill_(-1)
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()  # unrelated eager work and a sync
-        ccc.ccc_2way_many(probs)
+        ccc.ccc_2way_many(probs, **form_kw(form))
         sync()
         for (t, c, cnt), (rt, rc, rcnt) in zip(outs, ref):
             assert torch.equal(t, rt) and torch.equal(c, rc) and torch.equal(cnt, rcnt), rep

@@ -8,8 +8,8 @@ import oracle
 import oracle.brute
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import (assert_ccc_close, assert_ccc_identical, assert_tables_equal, dev, host,
-                      say)
+from gpu_util import (MFMA_FORMS, assert_ccc_close, assert_ccc_identical, assert_tables_equal,
+                      dev, form_kw, host, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -33,13 +33,14 @@ def check_counts(cnt, v, n_f, s):
     assert np.all(cnt[:, 5:] == 0)
 
 
+@pytest.mark.parametrize("form", MFMA_FORMS)
 @pytest.mark.parametrize("s", [2, 3, 4])
 @pytest.mark.parametrize("n_v,n_f,missing,extra", SHAPES)
-def test_multi_parity(s, n_v, n_f, missing, extra):
-    say("multi", s, n_v, n_f, missing, extra)
+def test_multi_parity(s, n_v, n_f, missing, extra, form):
+    say("multi", s, n_v, n_f, missing, extra, form)
     v = synth.multi_hw(n_v, n_f, s, seed=n_v * 3 + n_f + s, missing=missing,
                        ld=synth.ld_multi(n_f, extra))
-    t, c, cnt = run_multi(v, n_f, s)
+    t, c, cnt = run_multi(v, n_f, s, **form_kw(form))
     ot, oc = oracle.multi_two_way(v, n_f, s)
     assert_tables_equal(t, ot)
     assert_ccc_close(c, oc)

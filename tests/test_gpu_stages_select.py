@@ -6,11 +6,11 @@ import pytest
 import oracle
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import assert_ccc_close, assert_tables_equal, dev, host, say
+from gpu_util import FORMS, assert_ccc_close, assert_tables_equal, dev, form_kw, host, say
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["popcount", "mfma"]
+PATHS = FORMS
 
 
 def sync():
@@ -25,10 +25,10 @@ def test_2way_rows_concatenate_to_the_triangle(path):
     say("2way rows", path)
     v = synth.beta_hw(n, n_f, seed=901, missing=0.02)
     dv = dev(v)
-    t_full, c_full, _ = ccc.ccc_2way(dv, n_f, path=path)
+    t_full, c_full, _ = ccc.ccc_2way(dv, n_f, **form_kw(path))
     parts = []
     for i0, i1 in [(0, 1), (1, 57), (57, 128), (128, 129), (129, 299), (299, 300), (10, 10)]:
-        t, c, _ = ccc.ccc_2way_rows(dv, n_f, i0, i1, path=path)
+        t, c, _ = ccc.ccc_2way_rows(dv, n_f, i0, i1, **form_kw(path))
         sync()
         ot, oc = oracle.two_way(v, n_f, i0, i1)
         assert_tables_equal(host(t), ot)
@@ -48,14 +48,14 @@ def test_2way_rows_across_square_strips(path):
     say("2way rows across strips", path)
     v = synth.beta_hw(n, n_f, seed=907, missing=0.02)
     dv = dev(v)
-    t_full, c_full, _ = ccc.ccc_2way(dv, n_f, path=path)
+    t_full, c_full, _ = ccc.ccc_2way(dv, n_f, **form_kw(path))
     sync()
     ot, oc = oracle.two_way(v, n_f)
     assert_tables_equal(host(t_full), ot)
     assert_ccc_close(host(c_full), oc)
     parts = []
     for i0, i1 in [(0, 700), (700, 1030), (1030, 1100), (1100, 1500)]:
-        t, c, _ = ccc.ccc_2way_rows(dv, n_f, i0, i1, path=path)
+        t, c, _ = ccc.ccc_2way_rows(dv, n_f, i0, i1, **form_kw(path))
         sync()
         ot, oc = oracle.two_way(v, n_f, i0, i1)
         assert_tables_equal(host(t), ot)
@@ -73,10 +73,10 @@ def test_3way_rows_concatenate_to_the_tetrahedron(path):
     say("3way rows", path)
     v = synth.beta_hw(n, n_f, seed=902, missing=0.02)
     dv = dev(v)
-    t_full, c_full, _ = ccc.ccc_3way(dv, n_f, path=path)
+    t_full, c_full, _ = ccc.ccc_3way(dv, n_f, **form_kw(path))
     parts = []
     for i0, i1 in [(0, 5), (5, 64), (64, 65), (65, 88), (88, 90)]:
-        t, c, _ = ccc.ccc_3way_rows(dv, n_f, i0, i1, path=path)
+        t, c, _ = ccc.ccc_3way_rows(dv, n_f, i0, i1, **form_kw(path))
         sync()
         ot, oc = oracle.three_way(v, n_f, i0, i1)
         assert_tables_equal(host(t), ot)
@@ -103,7 +103,8 @@ def test_2way_select_matches_filtered_oracle(path):
     ot, oc = oracle.two_way(v, n_f)
     thr = threshold_between(oc.max(axis=1), 0.01)
     want = np.flatnonzero(oc.max(axis=1) >= thr)
-    found, idx, cc, tt = ccc.ccc_2way_select(dev(v), n_f, thr, cap=len(want) + 100, path=path)
+    found, idx, cc, tt = ccc.ccc_2way_select(dev(v), n_f, thr, cap=len(want) + 100,
+                                             **form_kw(path))
     assert found == len(want)
     idx, cc, tt = host(idx), host(cc), host(tt)
     order = np.argsort(idx)
@@ -111,11 +112,11 @@ def test_2way_select_matches_filtered_oracle(path):
     assert_tables_equal(tt[order], ot[want])
     assert_ccc_close(cc[order], oc[want])
     # a cap below the number found: the count is exact, the records a subset
-    found2, idx2, cc2, _ = ccc.ccc_2way_select(dev(v), n_f, thr, cap=7, path=path)
+    found2, idx2, cc2, _ = ccc.ccc_2way_select(dev(v), n_f, thr, cap=7, **form_kw(path))
     assert found2 == len(want) and len(host(idx2)) == 7
     assert set(host(idx2).tolist()) <= set(want.tolist())
     # threshold above every value: nothing kept
-    found3, _, _, _ = ccc.ccc_2way_select(dev(v), n_f, 2.0, cap=4, path=path)
+    found3, _, _, _ = ccc.ccc_2way_select(dev(v), n_f, 2.0, cap=4, **form_kw(path))
     assert found3 == 0
 
 
@@ -127,7 +128,7 @@ def test_3way_select_matches_filtered_oracle(path):
     ot, oc = oracle.three_way(v, n_f)
     thr = threshold_between(oc.max(axis=1), 0.005)
     want = np.flatnonzero(oc.max(axis=1) >= thr)
-    found, idx, cc, tt = ccc.ccc_3way_select(dev(v), n_f, thr, cap=len(want), path=path)
+    found, idx, cc, tt = ccc.ccc_3way_select(dev(v), n_f, thr, cap=len(want), **form_kw(path))
     assert found == len(want)
     idx, cc, tt = host(idx), host(cc), host(tt)
     order = np.argsort(idx)
