@@ -277,6 +277,28 @@ int ccc_2way_multi(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s
                    int32_t* tables, double* ccc, int32_t* counts, const ccc_opts* opts,
                    hipStream_t stream);
 
+/*
+ * ccc_3way_noalloc -- ccc_3way for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, validation and results as ccc_3way; it calls
+ * no hipMalloc, hipFree or other allocating routine (with kernel timing off).
+ * Its scratch (work-unit offsets, the counts when `counts` is NULL, and the
+ * complete-data Gram matrix) lives in a fixed device array of
+ * CCC_NOALLOC_SCRATCH_BYTES per device, kept until the process ends, instead
+ * of the library workspace.  CCC_ERR_RANGE when the unit offsets (8 bytes per
+ * pair of 64-row tiles, about n_v^2 / 1024 bytes) plus the counts (16 bytes
+ * per vector when `counts` is NULL) exceed it.  The Gram matrix (4 n_v^2
+ * bytes) is used only when it also fits (n_v up to about 2500); otherwise
+ * every unit takes the general form, with the same results.  Every call on a
+ * device shares that device's array: calls whose work overlaps on one device
+ * (two streams, or two host threads) race and give undefined results; the
+ * caller must order them.  The first call on a device looks up the array's
+ * address there (CCC_ERR_HIP if that fails).
+ */
+#define CCC_NOALLOC_SCRATCH_BYTES (24ull << 20)
+int ccc_3way_noalloc(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+                     double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream);
+
 /* Static text for a status code. */
 const char* ccc_status_string(int status);
 

@@ -7,7 +7,7 @@ turns negative status codes into :class:`CccError`.  Every step of the
 computation runs in the library's HIP kernels; there is no fallback.
 
 Functions carry the C names: :func:`ccc_2way`, :func:`ccc_3way`,
-:func:`ccc_2way_block`, :func:`ccc_2way_many`.
+:func:`ccc_2way_block`, :func:`ccc_2way_many`, :func:`ccc_3way_noalloc`, ...
 """
 from __future__ import annotations
 
@@ -68,6 +68,7 @@ def lib():
         opts_p = ctypes.POINTER(ccc_opts)
         L.ccc_2way.argtypes = [vp, i64, i64, i64, vp, vp, vp, opts_p, vp]
         L.ccc_3way.argtypes = [vp, i64, i64, i64, vp, vp, vp, opts_p, vp]
+        L.ccc_3way_noalloc.argtypes = [vp, i64, i64, i64, vp, vp, vp, opts_p, vp]
         L.ccc_2way_block.argtypes = [vp, i64, i64, vp, i64, i64, i64, vp, vp, vp, vp, opts_p, vp]
         L.ccc_2way_many.argtypes = [ctypes.POINTER(ccc_problem), cint, opts_p, vp]
         L.ccc_2way_rows.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp, vp, opts_p, vp]
@@ -76,7 +77,7 @@ def lib():
         sel_p = ctypes.POINTER(ccc_selection)
         L.ccc_2way_select.argtypes = [vp, i64, i64, i64, ctypes.c_double, sel_p, vp, opts_p, vp]
         L.ccc_3way_select.argtypes = [vp, i64, i64, i64, ctypes.c_double, sel_p, vp, opts_p, vp]
-        for f in (L.ccc_2way, L.ccc_3way, L.ccc_2way_block, L.ccc_2way_many, L.ccc_2way_rows,
+        for f in (L.ccc_2way, L.ccc_3way, L.ccc_3way_noalloc, L.ccc_2way_block, L.ccc_2way_many, L.ccc_2way_rows,
                   L.ccc_3way_rows, L.ccc_2way_select, L.ccc_3way_select, L.ccc_2way_multi):
             f.restype = cint
         L.ccc_timing_enable.argtypes = [cint]
@@ -230,6 +231,21 @@ def ccc_2way_multi(v, n_f, s, tables=None, ccc=None, counts=None, path="auto", g
 def ccc_3way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
              want_tables=True, want_ccc=True, stream=None, operands="auto"):
     """All triples i<j<k: returns (tables int32 [T,8], ccc float64 [T,8], counts)."""
+    return _three_way("ccc_3way", v, n_f, tables, ccc, counts, path, gamma, want_tables,
+                      want_ccc, stream, operands)
+
+
+def ccc_3way_noalloc(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMMA,
+                     want_tables=True, want_ccc=True, stream=None, operands="auto"):
+    """As :func:`ccc_3way`, through the entry point whose scratch is the
+    library's fixed per-device array (no device allocation inside the call;
+    outputs the caller does not pass are still allocated here, by torch)."""
+    return _three_way("ccc_3way_noalloc", v, n_f, tables, ccc, counts, path, gamma, want_tables,
+                      want_ccc, stream, operands)
+
+
+def _three_way(fn_name, v, n_f, tables, ccc, counts, path, gamma, want_tables, want_ccc, stream,
+               operands):
     torch = _torch()
     _check_input(v)
     n_v, ld = v.shape
@@ -245,9 +261,9 @@ def ccc_3way(v, n_f, tables=None, ccc=None, counts=None, path="auto", gamma=GAMM
     _check_out(ccc, (T, 8), torch.float64, "ccc")
     _check_out(counts, (n_v, 4), torch.int32, "counts")
     o = make_opts(path, gamma, operands=operands)
-    st = lib().ccc_3way(_ptr(v), n_v, n_f, ld, _ptr(tables), _ptr(ccc), _ptr(counts),
-                        ctypes.byref(o), _stream(stream))
-    _raise(st, "ccc_3way")
+    st = getattr(lib(), fn_name)(_ptr(v), n_v, n_f, ld, _ptr(tables), _ptr(ccc), _ptr(counts),
+                                 ctypes.byref(o), _stream(stream))
+    _raise(st, fn_name)
     return tables, ccc, counts
 
 

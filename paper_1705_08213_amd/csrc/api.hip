@@ -216,10 +216,47 @@ int two_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_be
 int64_t choose3(int64_t n) { return n < 3 ? 0 : n * (n - 1) / 2 * (n - 2) / 3; }
 int64_t choose2(int64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
 
+// Scratch of ccc_3way_noalloc: a fixed device array, one copy per device,
+// held until the process ends.  Host code never uses its name as an address:
+// the device address of each device's copy is looked up once (with that
+// device current) and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[CCC_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch;  // indexed by device ordinal; null until looked up
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CCC_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return CCC_ERR_HIP;
+    }
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return CCC_OK;
+}
+
+// The no-allocation form of a call: its scratch is the fixed array above
+// (`bytes` of it) instead of the library workspace.
+struct FixedScratch {
+  size_t bytes;
+};
+
 // All 3-way variants: dense first-index rows [i_begin, i_end) or selection.
+// With `fixed`, the scratch comes from there instead of the workspace: the
+// call returns CCC_ERR_RANGE if the unit offsets and counts do not fit, and
+// leaves the Gram matrix out (every unit then takes the general form, same
+// results) when it does not fit beside them.
 int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_begin,
               int64_t i_end, int32_t* tables, double* ccc, const ccc_selection* sel,
-              double threshold, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+              double threshold, int32_t* counts, const ccc_opts* opts, hipStream_t stream,
+              const FixedScratch* fixed = nullptr) {
   ccc_opts o;
   int st = resolve_opts(opts, &o);
   if (st) return st;
@@ -252,10 +289,17 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   const size_t offs_bytes = ((size_t)(ccc::grid_pairs(ug) + 1) * 8 + 255) / 256 * 256;
   const size_t cnt_bytes = counts ? 0 : ((size_t)n_v * 16 + 255) / 256 * 256;
   const int64_t g0 = i_begin / ccc::kUnitTile * ccc::kUnitTile, ng = n_v - g0;
-  const bool use_gram = o.path != CCC_PATH_POPCOUNT && ng <= kGramMaxRows && i_begin < row_end;
+  bool use_gram = o.path != CCC_PATH_POPCOUNT && ng <= kGramMaxRows && i_begin < row_end;
+  if (fixed) {
+    if (offs_bytes + cnt_bytes > fixed->bytes) return CCC_ERR_RANGE;
+    if (use_gram && (size_t)ng * (size_t)ng * 4 > fixed->bytes - offs_bytes - cnt_bytes)
+      use_gram = false;
+  }
   const size_t gram_bytes = use_gram ? (size_t)ng * (size_t)ng * 4 : 0;
   void* ws = nullptr;
-  if ((st = ccc::workspace(offs_bytes + cnt_bytes + gram_bytes, &ws))) return st;
+  if ((st = fixed ? noalloc_scratch(&ws)
+                  : ccc::workspace(offs_bytes + cnt_bytes + gram_bytes, &ws)))
+    return st;
   int32_t* cnt = counts ? counts : reinterpret_cast<int32_t*>(static_cast<char*>(ws) + offs_bytes);
   if (n_v < 3)
     return ccc::launch_count1_zero(v, ld, n_v, n_f, cnt, 0, zero, stream) == hipSuccess
@@ -443,6 +487,13 @@ int ccc_2way_many(const ccc_problem* probs, int n_probs, const ccc_opts* opts,
   if (f4 < 0) return f4;
   if (n_probs == 0) return CCC_OK;
   return ccc::run_many(probs, n_probs, o, f4 != 0, stream);
+}
+
+int ccc_3way_noalloc(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int32_t* tables,
+                     double* ccc, int32_t* counts, const ccc_opts* opts, hipStream_t stream) {
+  const FixedScratch fs{CCC_NOALLOC_SCRATCH_BYTES};
+  return three_way(v, n_v, n_f, ld, 0, n_v < 0 ? 0 : n_v, tables, ccc, nullptr, 0.0, counts,
+                   opts, stream, &fs);
 }
 
 void ccc_release_workspace(void) {

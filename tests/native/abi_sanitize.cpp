@@ -86,11 +86,13 @@ int main() {
          CCC_ERR_ARG);
 
   // 2-way / 3-way / rows / select validation
-  for (int way = 2; way <= 3; ++way) {
+  // way 4: the no-allocation 3-way entry point
+  for (int way = 2; way <= 4; ++way) {
     auto call = [&](const uint8_t* v, int64_t n, int64_t nf, int64_t ld, int32_t* t, double* c,
                     int32_t* cnt, const ccc_opts* o) {
-      return way == 2 ? ccc_2way(v, n, nf, ld, t, c, cnt, o, nullptr)
-                      : ccc_3way(v, n, nf, ld, t, c, cnt, o, nullptr);
+      return way == 2   ? ccc_2way(v, n, nf, ld, t, c, cnt, o, nullptr)
+             : way == 3 ? ccc_3way(v, n, nf, ld, t, c, cnt, o, nullptr)
+                        : ccc_3way_noalloc(v, n, nf, ld, t, c, cnt, o, nullptr);
     };
     int32_t* T = fk<int32_t>();
     double* C = fk<double>();
@@ -110,7 +112,7 @@ int main() {
     ccc_opts accum = opts(0, CCC_ACCUMULATE);
     EXPECT(call(fake(), 10, 100, 32, T, C, nullptr, &accum), CCC_ERR_ARG);
     EXPECT(call(nullptr, 0, 100, 32, nullptr, nullptr, nullptr, &dflt), CCC_OK);
-    EXPECT(call(fake(), way - 1, 100, 32, nullptr, nullptr, nullptr, &dflt), CCC_OK);
+    EXPECT(call(fake(), way == 2 ? 1 : 2, 100, 32, nullptr, nullptr, nullptr, &dflt), CCC_OK);
   }
   for (int way = 2; way <= 3; ++way) {
     auto rows = [&](int64_t n, int64_t i0, int64_t i1, int32_t* t, double* c) {
@@ -216,6 +218,15 @@ int main() {
                   CCC_ERR_HIP);
     }
   remove(tune);
+
+  // no-allocation 3-way: scratch limit, then (valid call) the device
+  // lookup of the scratch array, which fails cleanly without a GPU
+  EXPECT(ccc_3way_noalloc(fake(), 400000, 100, 32, fk<int32_t>(), fk<double>(), nullptr, &dflt,
+                          nullptr),
+         CCC_ERR_RANGE);
+  EXPECT(ccc_3way_noalloc(fake(), 10, 100, 32, fk<int32_t>(), fk<double>(), nullptr, &dflt,
+                          nullptr),
+         CCC_ERR_HIP);
 
   // timing hooks with nothing recorded
   ccc_timing_enable(1);

@@ -117,6 +117,11 @@ def call3(v=FAKE, n_v=10, n_f=100, ld=32, tables=FAKE, cc=FAKE, counts=None, opt
     return ccc.lib().ccc_3way(v, n_v, n_f, ld, tables, cc, counts, o, None)
 
 
+def call3n(v=FAKE, n_v=10, n_f=100, ld=32, tables=FAKE, cc=FAKE, counts=None, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return ccc.lib().ccc_3way_noalloc(v, n_v, n_f, ld, tables, cc, counts, o, None)
+
+
 def callb(va=FAKE, n_a=8, lda=32, vb=FAKE, n_b=9, ldb=32, n_f=100, tables=FAKE, ca=FAKE,
           cb=FAKE, cc=FAKE, flags=ccc.CCC_FINALIZE, path=0):
     o = ccc.make_opts(path, flags=flags)
@@ -124,7 +129,7 @@ def callb(va=FAKE, n_a=8, lda=32, vb=FAKE, n_b=9, ldb=32, n_f=100, tables=FAKE, 
                                     ctypes.byref(o), None)
 
 
-@pytest.mark.parametrize("fn", [call2, call3])
+@pytest.mark.parametrize("fn", [call2, call3, call3n])
 def test_validation_errors_common(fn):
     assert fn(v=None) == ccc.CCC_ERR_ARG
     assert fn(n_v=-1) == ccc.CCC_ERR_ARG
@@ -151,6 +156,21 @@ def test_range_limits():
     assert call3(n_f=ok_2way_but_not_3way, ld=ld) == ccc.CCC_ERR_RANGE
     assert callb(n_f=big, lda=(big + 3) // 4 // 16 * 16 + 16,
                  ldb=(big + 3) // 4 // 16 * 16 + 16) == ccc.CCC_ERR_RANGE
+
+
+def test_noalloc_3way_validation_and_scratch_limit():
+    """The no-allocation 3-way entry point validates like ccc_3way, and a
+    problem whose work-unit offsets (8 bytes per pair of 64-row tiles) cannot
+    fit its fixed scratch is a range error, caught before any HIP call."""
+    big = I32MAX // 8 + 1
+    assert call3n(n_f=big, ld=(big + 3) // 4 // 16 * 16 + 16) == ccc.CCC_ERR_RANGE
+    assert call3n(ld=(1 << 28) + 16) == ccc.CCC_ERR_RANGE
+    assert call3n(n_v=2642246) == ccc.CCC_ERR_ARG  # C(n_v,3) * 8 past int64 indexing
+    # 400000 rows: 6250 tiles, about 19.5 million tile pairs, 156 MB of offsets
+    assert call3n(n_v=400000) == ccc.CCC_ERR_RANGE
+    assert call3n(n_v=400000, counts=FAKE) == ccc.CCC_ERR_RANGE
+    assert call3n(v=None, n_v=0) == ccc.CCC_OK
+    assert call3n(n_v=2, tables=None, cc=None) == ccc.CCC_OK
 
 
 def test_empty_problems_return_ok_without_work():
