@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libccc.so")
 
 SOURCES = ["api.hip", "count1.hip", "pop2.hip", "mfma2.hip", "pop3.hip", "mfma3.hip", "many.hip",
-           "multi2.hip", "timing.hip"]
+           "multi2.hip", "timing.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -200,6 +200,11 @@ struct Triple3Args {
 
 enum Path { kPathPopcount = 1, kPathMfma = 2 };
 
+// Kernel-shape table (tune.hip): kinds of launch, and the variant the table
+// picks for a problem of n_v vectors over n_f fields (0 .. n_variants - 1).
+enum TuneKind { kTuneManyMfma = 0, kTuneManyPopcount = 1 };
+int tune_pick(int kind, int64_t n_v, int64_t n_f, int n_variants);
+
 // Optional event timing around the main kernel of a launcher (no-ops unless
 // enabled through ccc_timing_enable).
 void timing_begin(const char* name, hipStream_t stream);

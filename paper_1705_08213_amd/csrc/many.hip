@@ -163,58 +163,10 @@ __global__ __launch_bounds__(256) void many_pop_kernel(const ProbDesc* __restric
   }
 }
 
-// ---------------------------------------------------------------------------
-// Tune table: lines "n_v_max n_f_max path variant" (path = mfma | popcount);
-// the first line whose bounds hold picks the variant.  Read once from
-// $CCC_TUNE_FILE, else from tune_gfx950.txt next to the library.
-// ---------------------------------------------------------------------------
-
-struct TuneRule {
-  int64_t nv_max, nf_max;
-  int path;
-  int variant;
-};
-
-std::once_flag g_tune_once;
-std::vector<TuneRule> g_tune;
-
-void load_tune_table() {
-  std::string path;
-  if (const char* env = getenv("CCC_TUNE_FILE")) {
-    path = env;
-  } else {
-    Dl_info info;
-    if (dladdr(reinterpret_cast<void*>(&load_tune_table), &info) && info.dli_fname) {
-      path = info.dli_fname;
-      size_t slash = path.rfind('/');
-      path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) +
-             "/tune_gfx950.txt";
-    }
-  }
-  FILE* f = path.empty() ? nullptr : fopen(path.c_str(), "r");
-  if (!f) return;
-  char line[256];
-  while (fgets(line, sizeof line, f)) {
-    if (line[0] == '#') continue;
-    long long nv, nf;
-    char p[32];
-    int var;
-    if (sscanf(line, "%lld %lld %31s %d", &nv, &nf, p, &var) != 4) continue;
-    TuneRule r{nv, nf, strcmp(p, "popcount") == 0 ? CCC_PATH_POPCOUNT : CCC_PATH_MFMA, var};
-    if (r.variant >= 0 && r.variant < kVariants) g_tune.push_back(r);
-  }
-  fclose(f);
-}
-
+// Tile variant of a problem from the kernel-shape table (tune.hip).
 int pick_variant(int64_t n_v, int64_t n_f, int path) {
-  if (const char* env = getenv("CCC_MANY_VARIANT")) {  // tuner override
-    int v = atoi(env);
-    if (v >= 0 && v < kVariants) return v;
-  }
-  std::call_once(g_tune_once, load_tune_table);
-  for (const TuneRule& r : g_tune)
-    if (r.path == path && n_v <= r.nv_max && n_f <= r.nf_max) return r.variant;
-  return 0;
+  return tune_pick(path == CCC_PATH_POPCOUNT ? kTuneManyPopcount : kTuneManyMfma, n_v, n_f,
+                   kVariants);
 }
 
 // ---------------------------------------------------------------------------

@@ -13,7 +13,13 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_1705_08213_amd", "csrc")
-SOURCES = ["api", "count1", "pop2", "mfma2", "pop3", "mfma3", "many", "multi2", "timing"]
+
+def _sources():
+    from paper_1705_08213_amd.build import SOURCES
+    return [os.path.splitext(f)[0] for f in SOURCES]
+
+
+SOURCES = _sources()
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
