@@ -182,16 +182,17 @@ int two_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_be
                ? CCC_OK
                : CCC_ERR_HIP;
   }
-  int32_t* cnt = counts;
-  if (!cnt) {
-    void* ws = nullptr;
-    if ((st = ccc::workspace((size_t)n_v * 16, &ws))) return st;
-    cnt = static_cast<int32_t*>(ws);
-  }
+  // workspace: the counts (unless the caller's), then the MFMA path's
+  // complete-data flag
+  const size_t cnt_bytes = counts ? 0 : ((size_t)n_v * 16 + 255) / 256 * 256;
+  void* ws = nullptr;
+  if ((st = ccc::workspace(cnt_bytes + 256, &ws))) return st;
+  int32_t* cnt = counts ? counts : static_cast<int32_t*>(ws);
   if (ccc::launch_count1_zero(v, ld, n_v, n_f, cnt, 0, zero, stream) != hipSuccess)
     return CCC_ERR_HIP;
   if (row_end <= i_begin) return CCC_OK;
   ccc::Pair2Args a{};
+  a.complete = reinterpret_cast<int*>(static_cast<char*>(ws) + cnt_bytes);
   a.va = v; a.lda = ld; a.n_a = n_v;
   a.vb = v; a.ldb = ld; a.n_b = n_v;
   a.n_f = n_f;
@@ -395,12 +396,13 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   if (!aligned16(tables) || !aligned16(ccc) || !aligned16(counts_a) || !aligned16(counts_b))
     return CCC_ERR_ALIGN;
   if (n_a == 0 || n_b == 0) return CCC_OK;
-  // an accumulating call also needs this chunk's own counts (workspace)
+  // workspace: an accumulating call's own chunk counts, or else the MFMA
+  // path's complete-data flag
   int32_t* chunk_a = counts_a;
   int32_t* chunk_b = counts_b;
+  void* ws = nullptr;
+  if ((st = ccc::workspace(acc ? (size_t)(n_a + n_b) * 16 : 256, &ws))) return st;
   if (acc) {
-    void* ws = nullptr;
-    if ((st = ccc::workspace((size_t)(n_a + n_b) * 16, &ws))) return st;
     chunk_a = static_cast<int32_t*>(ws);
     chunk_b = chunk_a + 4 * n_a;
     if (ccc::launch_count1(va, lda, n_a, n_f, chunk_a, 0, stream) != hipSuccess ||
@@ -429,6 +431,7 @@ int ccc_2way_block(const uint8_t* va, int64_t n_a, int64_t lda, const uint8_t* v
   a.row_end = n_a;
   a.p_base = 0;
   a.sel = ccc::Select{nullptr, 0, 0.0, nullptr, nullptr, nullptr};
+  a.complete = acc ? nullptr : static_cast<int*>(ws);
   return ccc::run_pair2(a, o.path, stream);
 }
 

@@ -18,6 +18,13 @@ typedef unsigned u4 __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Byte pointer into global memory.  A pointer rebuilt from integers (a
+// wave-uniform row base read from lane 0) or loaded from a table is generic
+// to the compiler, and loads through it take the flat form (no scalar base,
+// counted against the LDS counter too); through this type they take the
+// global form.
+typedef const __attribute__((address_space(1))) uint8_t* gbytes;
+
 // 16 fields of the missing code (0b10 each).
 constexpr unsigned kAllMissing = 0xAAAAAAAAu;
 constexpr unsigned kEven = 0x55555555u;

@@ -44,6 +44,10 @@ struct Pair2Args {
   int64_t p_base;
   int64_t sq_offset;          // first square tile of the row range (triangle)
   Select sel;                 // threshold selection (sel.count != null) instead of dense output
+  // Device flag (one int) that launch_mfma2 sets to 1 when every row of A and
+  // B has all n_f fields present, 0 otherwise; null: no such check (each
+  // workgroup tile votes for itself).  Only for calls that do not accumulate.
+  int* complete;
 };
 
 // Largest n_f for which the MFMA kernels may take fp4 operands (their fp32

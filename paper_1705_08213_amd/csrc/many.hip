@@ -101,6 +101,7 @@ __device__ __forceinline__ Pair2Args pair_args(const ProbDesc& p, double gamma) 
   a.p_base = 0;
   a.sq_offset = 0;
   a.sel = Select{nullptr, 0, 0.0, nullptr, nullptr, nullptr};
+  a.complete = nullptr;
   return a;
 }
 

@@ -4,12 +4,26 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "common.h"
 #include "kernels.h"
 
 namespace ccc {
 namespace tile2 {
+
+// f(integral_constant<int, I>) for I = 0 .. N - 1, unrolled in the source:
+// loops whose bodies index register arrays stay in registers whatever the
+// compiler's unrolling limits (a loop it leaves rolled turns such an array
+// into scratch memory).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
 
 // Output of one pair (i, j) with table t (Eqs. (2)-(3)) and the factors wi,
 // wj of its two vectors (read on valid lanes only).  Dense mode stores the
@@ -308,6 +322,26 @@ __device__ __forceinline__ v8i nibbles32(unsigned x0, unsigned x1) {
              (int)((x1 >> 2) & kNib2), 0, 0, 0, 0};
 }
 
+// nibbles32(rho1_16_f4<true>(w0), rho1_16_f4<true>(w1)) for words of
+// complete data (codes 00, 01, 11), in nine operations instead of twelve:
+// per field (hi, lo) -> (hi, lo & ~hi), one v_bitop3 (0x20 = c & a & ~b) of
+// the word and its hi bits moved to the field's bit 0 (h); the odd fields
+// are shifted down by two first, word and hi bits alike.  The pair shifts
+// carry w1's low bits into bits 30-31 (31 for s) of the w0 results, which
+// kEven2 and kNib2 drop.
+__device__ __forceinline__ v8i rho1_nibbles_complete(unsigned w0, unsigned w1) {
+  unsigned s0, s1, t0, t1, q0, q1;
+  shr_pair<1>(w0, w1, s0, s1);
+  const unsigned h0 = s0 & kEven2, h1 = s1 & kEven2;
+  shr_pair<2>(w0, w1, t0, t1);
+  shr_pair<2>(h0, h1, q0, q1);
+  return v8i{(int)__builtin_amdgcn_bitop3_b32(w0, h0, kNib2, 0x20),
+             (int)__builtin_amdgcn_bitop3_b32(t0, q0, kNib2, 0x20),
+             (int)__builtin_amdgcn_bitop3_b32(w1, h1, kNib2, 0x20),
+             (int)__builtin_amdgcn_bitop3_b32(t1, q1, kNib2, 0x20),
+             0, 0, 0, 0};
+}
+
 __device__ __forceinline__ v8i operand_f4(const unsigned (&x0)[2], const unsigned (&x1)[2]) {
   return v8i{(int)x0[0], (int)x0[1], (int)x1[0], (int)x1[1], 0, 0, 0, 0};
 }
@@ -396,12 +430,13 @@ __device__ __forceinline__ void stage_row(const uint8_t* src, u4* dst) {
 // earlier is free.  Every wave of the workgroup must call it; inactive
 // waves only copy their blocks.  Then the masked tail step of the active
 // waves from plain loads (pa, pb: this wave's rows, with the lane's 16g
-// byte offset).
-template <int WM, int WN, typename Step>
+// byte offset), taken by `tail` (whose fields past n_f read as missing).
+template <int WM, int WN, typename Step, typename Tail>
 __device__ __forceinline__ void wg_loop_f4(const Pair2Args& a, int64_t I0, int64_t J0,
                                            bool active, const uint8_t* const (&pa)[WM],
                                            const uint8_t* const (&pb)[WN],
-                                           u4 (*stage)[2 * WM + 2 * WN][64], Step step) {
+                                           u4 (*stage)[2 * WM + 2 * WN][64], Step step,
+                                           Tail tail) {
   constexpr int NB = 2 * WM + 2 * WN, BPW = (NB + 3) / 4;  // blocks, blocks per wave
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
@@ -456,7 +491,7 @@ __device__ __forceinline__ void wg_loop_f4(const Pair2Args& a, int64_t I0, int64
     for (int m = 0; m < WM; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kt + 16 * g, a.n_f);
 #pragma unroll
     for (int n = 0; n < WN; ++n) xb[n] = load_fields64(pb[n] - 16 * g, kt + 16 * g, a.n_f);
-    step(xa, xb);
+    tail(xa, xb);
   }
 }
 
@@ -598,12 +633,12 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     for (int m = 0; m < WM; ++m)
 #pragma unroll
       for (int n = 0; n < WN; ++n) acc1[m][n] = Acc{0, 0, 0, 0};
-    if constexpr (F4)
-      wg_loop_f4<WM, WN>(a, I0, J0, true, pa, pb, stage,
-                         [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
-                           mma_superstep_rho1_f4<WM, WN, false>(ca, cb, acc1);
-                         });
-    else
+    if constexpr (F4) {
+      auto step1 = [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
+        mma_superstep_rho1_f4<WM, WN, false>(ca, cb, acc1);
+      };
+      wg_loop_f4<WM, WN>(a, I0, J0, true, pa, pb, stage, step1, step1);
+    } else
       wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
         mma_superstep_rho1<WM, WN>(ca, cb, acc1);
       });
@@ -650,10 +685,10 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[m][n][e] = Acc{0, 0, 0, 0};
   if constexpr (F4) {
-    wg_loop_f4<WM, WN>(a, I0, J0, active, pa, pb, stage,
-                       [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
-                         mma_superstep_f4u<WM, WN>(xa, xb, acc);
-                       });
+    auto step = [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
+      mma_superstep_f4u<WM, WN>(xa, xb, acc);
+    };
+    wg_loop_f4<WM, WN>(a, I0, J0, active, pa, pb, stage, step, step);
     if (!active) return;
   } else
     wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
@@ -695,6 +730,126 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
   }
 }
 
+// Wave tile of a call whose every row of A and B has all n_f fields
+// present (P = 1 on every field): only C11 = sum rho_i(1) rho_j(1) is
+// multiplied, and the table follows from the allele counts n(1):
+//   C10 = 2 n_i(1) - C11,  C01 = 2 n_j(1) - C11,
+//   C00 = 4 n_f - 2 n_i(1) - 2 n_j(1) + C11.
+// One plane needs a quarter of the accumulators of the general form, so a
+// wave holds a (16 WM) x (16 WN) tile four times the size, and a workgroup
+// of 2 x 2 such waves stages 2 WM + 2 WN row blocks per step for four times
+// the pairs: half the bytes per pair that travel from L2, and rho(1) of each
+// staged block feeds 2 WN (rows i) or 2 WM (rows j) MFMAs per half step.
+// Both operand formats stage through LDS.  Every wave of the workgroup must
+// call it; `outs` is this wave's 2 KB of LDS for staging its CCC stores.
+template <int WM, int WN, bool F4>
+__device__ __forceinline__ void mfma2_complete_wave_tile(const Pair2Args& a, int64_t row0,
+                                                         int64_t col0,
+                                                         u4 (*stage)[2 * WM + 2 * WN][64],
+                                                         u4* outs) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+  const int wave = threadIdx.x >> 6;
+  // no pair i < j in this wave tile
+  const bool active = row0 < a.n_a && col0 < a.n_b && !(a.tri && row0 >= col0 + 16 * WN - 1);
+  const int64_t I0 = row0 - (wave & 1) * 16 * WM, J0 = col0 - (wave >> 1) * 16 * WN;
+  const uint8_t* pa[WM];
+  const uint8_t* pb[WN];
+#pragma unroll
+  for (int m = 0; m < WM; ++m) {
+    const int64_t r = row0 + 16 * m + rl;
+    pa[m] = a.va + (r < a.n_a ? r : a.n_a - 1) * a.lda + 16 * g;
+  }
+#pragma unroll
+  for (int n = 0; n < WN; ++n) {
+    const int64_t r = col0 + 16 * n + rl;
+    pb[n] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
+  }
+  using Acc = std::conditional_t<F4, v4f, v4i>;
+  Acc acc[WM][WN];
+#pragma unroll
+  for (int m = 0; m < WM; ++m)
+#pragma unroll
+    for (int n = 0; n < WN; ++n) acc[m][n] = Acc{0, 0, 0, 0};
+  // `complete`: every field of the step is inside n_f (no padding code)
+  auto body = [&](const u4 (&xa)[WM], const u4 (&xb)[WN], auto complete) {
+    if constexpr (F4) {
+      auto rho1_pair = [&](unsigned w0, unsigned w1) {
+        if constexpr (complete.value)
+          return rho1_nibbles_complete(w0, w1);
+        else
+          return nibbles32(rho1_16_f4<false>(w0), rho1_16_f4<false>(w1));
+      };
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v8i b1[WN];
+#pragma unroll
+        for (int n = 0; n < WN; ++n)
+          b1[n] = rho1_pair(word_of(xb[n], 2 * h), word_of(xb[n], 2 * h + 1));
+#pragma unroll
+        for (int m = 0; m < WM; ++m) {
+          const v8i a1 = rho1_pair(word_of(xa[m], 2 * h), word_of(xa[m], 2 * h + 1));
+#pragma unroll
+          for (int n = 0; n < WN; ++n) acc[m][n] = mfma_f4(a1, b1[n], acc[m][n]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v4i b1[WN];
+#pragma unroll
+        for (int n = 0; n < WN; ++n) b1[n] = unpack16_rho1(word_of(xb[n], q));
+#pragma unroll
+        for (int m = 0; m < WM; ++m) {
+          const v4i a1 = unpack16_rho1(word_of(xa[m], q));
+#pragma unroll
+          for (int n = 0; n < WN; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1[n], acc[m][n], 0, 0, 0);
+        }
+      }
+    }
+  };
+  wg_loop_f4<WM, WN>(
+      a, I0, J0, active, pa, pb, stage,
+      [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) { body(xa, xb, std::true_type{}); },
+      [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) { body(xa, xb, std::false_type{}); });
+  if (!active) return;
+
+  // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
+  const int nf4 = (int)(4 * a.n_f);
+  double wj[WN][2];
+  int n1j[WN];
+#pragma unroll
+  for (int n = 0; n < WN; ++n) {
+    const int64_t j = col0 + 16 * n + rl;
+    side_factors(a, 1, j, wj[n]);
+    n1j[n] = reinterpret_cast<const v4i*>(a.counts_b)[j < a.n_b ? j : a.n_b - 1].y;
+  }
+  static_for<WM>([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = row0 + 16 * m + 4 * g + e;
+      const int n1i = reinterpret_cast<const v4i*>(a.counts_a)[i < a.n_a ? i : a.n_a - 1].y;
+      double wi[2];
+      side_factors(a, 0, i, wi);
+#pragma unroll
+      for (int n = 0; n < WN; ++n) {
+        const int64_t j = col0 + 16 * n + rl;
+        int c11;
+        if constexpr (F4)
+          c11 = f4_count(acc[m][n][e]);
+        else
+          c11 = acc[m][n][e];
+        const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
+        emit_pair_staged(a, valid, i, j,
+                         v4i{nf4 - 2 * n1i - 2 * n1j[n] + c11, 2 * n1j[n] - c11, 2 * n1i - c11,
+                             c11},
+                         wi, wj[n], outs);
+      }
+    }
+  });
+}
+
 // Complete-data workgroup tile (every one of its rows has all n_f fields
 // present, as the workgroup has voted): the one-plane product C11 of the
 // whole (32 WM) x (32 WN) tile is computed by all four waves together, each
@@ -710,19 +865,26 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
                                                     v4i (*part)[16][64]) {
   constexpr int TM = 2 * WM, TN = 2 * WN;  // 16x16 blocks of the workgroup tile
   static_assert(TM == 8 && TN == 4, "the LDS halves hold 4 x 4 blocks");
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
   const int g = lane >> 4, rl = lane & 15;
-  const uint8_t* pa[TM];
-  const uint8_t* pb[TN];
+  // The loads: a wave-uniform base per block (its first row,
+  // clamped; halves read from lane 0 so that it lives in scalar registers)
+  // plus a 32-bit lane offset (r - rf < 16 rows of at most 2^28 bytes), so
+  // that each load takes the scalar-base form and a step costs no vector
+  // address arithmetic.
+  gbytes base[TM + TN];
+  uint32_t off[TM + TN];
 #pragma unroll
-  for (int m = 0; m < TM; ++m) {
-    const int64_t r = I0 + 16 * m + rl;
-    pa[m] = a.va + (r < a.n_a ? r : a.n_a - 1) * a.lda + 16 * g;
-  }
-#pragma unroll
-  for (int n = 0; n < TN; ++n) {
-    const int64_t r = J0 + 16 * n + rl;
-    pb[n] = a.vb + (r < a.n_b ? r : a.n_b - 1) * a.ldb + 16 * g;
+  for (int b = 0; b < TM + TN; ++b) {
+    const bool rows_i = b < TM;
+    const int64_t n = rows_i ? a.n_a : a.n_b, ld = rows_i ? a.lda : a.ldb;
+    const int64_t r0 = rows_i ? I0 + 16 * b : J0 + 16 * (b - TM);
+    const int64_t rf = r0 < n ? r0 : n - 1, r = r0 + rl < n ? r0 + rl : n - 1;
+    const uint64_t bp = (uint64_t)((rows_i ? a.va : a.vb) + rf * ld);
+    base[b] = (gbytes)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
+    off[b] = (uint32_t)((r - rf) * ld + 16 * g);
   }
   using Acc = std::conditional_t<F4, v4f, v4i>;
   Acc acc[TM][TN];
@@ -734,17 +896,22 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
   // `complete`: every field of the step is inside n_f (no padding code)
   auto body = [&](const u4 (&xa)[TM], const u4 (&xb)[TN], auto complete) {
     if constexpr (F4) {
+      // rho(1) nibbles of two words: the short form on whole steps of
+      // complete data, the padding-aware one on the last step
+      auto rho1_pair = [&](unsigned w0, unsigned w1) {
+        if constexpr (complete.value)
+          return rho1_nibbles_complete(w0, w1);
+        else
+          return nibbles32(rho1_16_f4<false>(w0), rho1_16_f4<false>(w1));
+      };
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         v8i b1[TN];
 #pragma unroll
-        for (int n = 0; n < TN; ++n)
-          b1[n] = nibbles32(rho1_16_f4<complete.value>(word_of(xb[n], 2 * h)),
-                            rho1_16_f4<complete.value>(word_of(xb[n], 2 * h + 1)));
+        for (int n = 0; n < TN; ++n) b1[n] = rho1_pair(word_of(xb[n], 2 * h), word_of(xb[n], 2 * h + 1));
 #pragma unroll
         for (int m = 0; m < TM; ++m) {
-          const v8i a1 = nibbles32(rho1_16_f4<complete.value>(word_of(xa[m], 2 * h)),
-                                   rho1_16_f4<complete.value>(word_of(xa[m], 2 * h + 1)));
+          const v8i a1 = rho1_pair(word_of(xa[m], 2 * h), word_of(xa[m], 2 * h + 1));
 #pragma unroll
           for (int n = 0; n < TN; ++n) acc[m][n] = mfma_f4(a1, b1[n], acc[m][n]);
         }
@@ -772,19 +939,27 @@ __device__ __forceinline__ void mfma2_coop_complete(const Pair2Args& a, int64_t 
   const int64_t e_full = s_end < nfull ? s_end : nfull;
   for (int64_t st = s_begin; st < e_full; ++st) {
     u4 xa[TM], xb[TN];
+    // 32-bit lane offsets: the bytes read lie below 16 ld <= 2^32
+    const uint32_t so = (uint32_t)st * 64u;
 #pragma unroll
-    for (int m = 0; m < TM; ++m) xa[m] = *reinterpret_cast<const u4*>(pa[m] + st * 64);
+    for (int m = 0; m < TM; ++m)
+      xa[m] = *reinterpret_cast<const __attribute__((address_space(1))) u4*>(base[m] +
+                                                                           (off[m] + so));
 #pragma unroll
-    for (int n = 0; n < TN; ++n) xb[n] = *reinterpret_cast<const u4*>(pb[n] + st * 64);
+    for (int n = 0; n < TN; ++n)
+      xb[n] = *reinterpret_cast<const __attribute__((address_space(1))) u4*>(base[TM + n] +
+                                                                           (off[TM + n] + so));
     body(xa, xb, std::true_type{});
   }
   if (nfull >= s_begin && nfull < s_end) {
     const int64_t kb = nfull * 64 + 16 * g;
     u4 xa[TM], xb[TN];
 #pragma unroll
-    for (int m = 0; m < TM; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
+    for (int m = 0; m < TM; ++m)
+      xa[m] = load_fields64((const uint8_t*)(base[m] + off[m] - 16 * g), kb, a.n_f);
 #pragma unroll
-    for (int n = 0; n < TN; ++n) xb[n] = load_fields64(pb[n] - 16 * g, kb, a.n_f);
+    for (int n = 0; n < TN; ++n)
+      xb[n] = load_fields64((const uint8_t*)(base[TM + n] + off[TM + n] - 16 * g), kb, a.n_f);
     body(xa, xb, std::false_type{});
   }
 

@@ -118,9 +118,10 @@ def test_2way_paths_agree_and_are_deterministic():
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("n_v,n_f", [(200, 3001), (300, 512), (70, 9)])
 def test_2way_complete_data_and_single_missing_entry(path, n_v, n_f):
-    """Complete inputs take the one-plane path on the MFMA side; one missing
-    entry in one row sends only the tiles holding that row to the general
-    path.  Both must match the oracle."""
+    """Complete inputs take the complete-data kernel on the MFMA side; with
+    one missing entry in one row the general kernel runs, and only its
+    tiles holding that row use the four-plane form.  Both must match the
+    oracle."""
     say("2way complete", path, n_v, n_f)
     v = synth.beta_hw(n_v, n_f, seed=77 + n_v, missing=0.0)
     t, c, _ = run2(v, n_f, path)

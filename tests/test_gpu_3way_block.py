@@ -158,18 +158,20 @@ def test_block_one_shot(path, n_a, n_b, n_f, missing):
     assert_ccc_close(host(cc), oc)
 
 
+@pytest.mark.parametrize("n_a,n_b", [(200, 150), (600, 300)])
 @pytest.mark.parametrize("path", PATHS)
-def test_block_complete_data_and_one_missing_entry(path):
-    """Complete A and B take the workgroup-cooperative one-plane form (MFMA)
-    in a one-shot block call; one missing entry in B sends only the
-    workgroups holding that row back to the general form."""
+def test_block_complete_data_and_one_missing_entry(path, n_a, n_b):
+    """Complete A and B take the complete-data kernel (MFMA) in a one-shot
+    block call; with one missing entry in B the general kernel runs, and
+    its workgroups whose rows are all complete take the cooperative
+    one-plane form."""
     import torch
-    n_a, n_b, n_f = 200, 150, 3001
-    say("block complete", path)
+    n_f = 3001
+    say("block complete", path, n_a, n_b)
     va = synth.beta_hw(n_a, n_f, seed=61, missing=0.0)
     vb = synth.beta_hw(n_b, n_f, seed=62, missing=0.0)
     codes = oracle.brute.unpack_codes(vb, n_f)
-    codes[77, 1234] = 2
+    codes[n_b // 2, 1234] = 2
     vb2 = synth.pack_codes(codes, pad_value=-1)
     for b in (vb, vb2):
         tables = torch.empty((n_a, n_b, 4), dtype=torch.int32, device="cuda")

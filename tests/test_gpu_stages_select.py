@@ -18,12 +18,18 @@ def sync():
     torch.cuda.synchronize()
 
 
+# missing 0: every row complete, so the MFMA forms take the complete-data
+# kernel (256 x 128 workgroup tiles) instead of the general one
+MISSING = [0.02, 0.0]
+
+
+@pytest.mark.parametrize("missing", MISSING)
 @pytest.mark.parametrize("path", PATHS)
-def test_2way_rows_concatenate_to_the_triangle(path):
+def test_2way_rows_concatenate_to_the_triangle(path, missing):
     import torch
     n, n_f = 300, 1537
-    say("2way rows", path)
-    v = synth.beta_hw(n, n_f, seed=901, missing=0.02)
+    say("2way rows", path, missing)
+    v = synth.beta_hw(n, n_f, seed=901, missing=missing)
     dv = dev(v)
     t_full, c_full, _ = ccc.ccc_2way(dv, n_f, **form_kw(path))
     parts = []
@@ -39,14 +45,16 @@ def test_2way_rows_concatenate_to_the_triangle(path):
     assert torch.equal(torch.cat([p[1] for p in parts]), c_full)
 
 
+@pytest.mark.parametrize("missing", MISSING)
 @pytest.mark.parametrize("path", PATHS)
-def test_2way_rows_across_square_strips(path):
-    # 1500 rows are 12 square rows of 128: the MFMA launch walks them in
-    # strips of 8 (one whole, one partial); ranges start and end inside strips
+def test_2way_rows_across_square_strips(path, missing):
+    # 1500 rows are 12 square rows of 128 (6 of 256 for complete data): the
+    # MFMA launch walks them in strips of 8 (one whole, one partial); ranges
+    # start and end inside strips and squares
     import torch
     n, n_f = 1500, 300
-    say("2way rows across strips", path)
-    v = synth.beta_hw(n, n_f, seed=907, missing=0.02)
+    say("2way rows across strips", path, missing)
+    v = synth.beta_hw(n, n_f, seed=907, missing=missing)
     dv = dev(v)
     t_full, c_full, _ = ccc.ccc_2way(dv, n_f, **form_kw(path))
     sync()
@@ -95,11 +103,12 @@ def threshold_between(values, keep_fraction):
     return 0.5 * (u[k - 1] + u[k])
 
 
+@pytest.mark.parametrize("missing", MISSING)
 @pytest.mark.parametrize("path", PATHS)
-def test_2way_select_matches_filtered_oracle(path):
+def test_2way_select_matches_filtered_oracle(path, missing):
     n, n_f = 257, 2001
-    say("2way select", path)
-    v = synth.beta_hw(n, n_f, seed=903, missing=0.02)
+    say("2way select", path, missing)
+    v = synth.beta_hw(n, n_f, seed=903, missing=missing)
     ot, oc = oracle.two_way(v, n_f)
     thr = threshold_between(oc.max(axis=1), 0.01)
     want = np.flatnonzero(oc.max(axis=1) >= thr)
