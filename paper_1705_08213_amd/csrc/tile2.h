@@ -579,18 +579,17 @@ __device__ __forceinline__ void mma_superstep(const u4 (&pa)[WM], const u4 (&pb)
 
 // One wave's (16 WM) x (16 WN) tile of pairs with first row row0 and first
 // column col0 (see the design notes above); wave w of the workgroup holds
-// the tile at (I0 + (w & 1) 16 WM, J0 + (w >> 1) 16 WN).  int8 form: waves
-// whose tile holds no pair to compute return at once and no barrier is
-// used.  fp4 form: every wave of the workgroup must call it (the rows are
-// staged for the workgroup, `stage`: two buffers of 2 WM + 2 WN row blocks
-// of 1 KB); such waves only take part in the copies.
+// the tile at (I0 + (w & 1) 16 WM, J0 + (w >> 1) 16 WN).  Both operand
+// formats stage the rows for the workgroup (`stage`: two buffers of
+// 2 WM + 2 WN row blocks of 1 KB), so every wave of the workgroup must call
+// it; waves whose tile holds no pair to compute only take part in the
+// copies.
 template <int WM, int WN, bool F4>
 __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0, int64_t col0,
                                                 u4 (*stage)[2 * WM + 2 * WN][64]) {
   const int lane = threadIdx.x & 63;
   // no pair i < j in this wave tile
   const bool active = row0 < a.n_a && col0 < a.n_b && !(a.tri && row0 >= col0 + 16 * WN - 1);
-  if (!F4 && !active) return;
   const int g = lane >> 4, rl = lane & 15;
   const int wave = threadIdx.x >> 6;
   const int64_t I0 = row0 - (wave & 1) * 16 * WM, J0 = col0 - (wave >> 1) * 16 * WN;
@@ -633,15 +632,13 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     for (int m = 0; m < WM; ++m)
 #pragma unroll
       for (int n = 0; n < WN; ++n) acc1[m][n] = Acc{0, 0, 0, 0};
-    if constexpr (F4) {
-      auto step1 = [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
+    auto step1 = [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
+      if constexpr (F4)
         mma_superstep_rho1_f4<WM, WN, false>(ca, cb, acc1);
-      };
-      wg_loop_f4<WM, WN>(a, I0, J0, true, pa, pb, stage, step1, step1);
-    } else
-      wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
+      else
         mma_superstep_rho1<WM, WN>(ca, cb, acc1);
-      });
+    };
+    wg_loop_f4<WM, WN>(a, I0, J0, true, pa, pb, stage, step1, step1);
     const int nf4 = (int)(4 * a.n_f);
     double wj[WN][2];
     int n1j[WN];
@@ -684,16 +681,14 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
     for (int n = 0; n < WN; ++n)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[m][n][e] = Acc{0, 0, 0, 0};
-  if constexpr (F4) {
-    auto step = [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
+  auto step = [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) {
+    if constexpr (F4)
       mma_superstep_f4u<WM, WN>(xa, xb, acc);
-    };
-    wg_loop_f4<WM, WN>(a, I0, J0, active, pa, pb, stage, step, step);
-    if (!active) return;
-  } else
-    wave_loop<WM, WN>(pa, pb, g, a.n_f, [&](const u4 (&ca)[WM], const u4 (&cb)[WN]) {
-      mma_superstep<WM, WN>(ca, cb, acc);
-    });
+    else
+      mma_superstep<WM, WN>(xa, xb, acc);
+  };
+  wg_loop_f4<WM, WN>(a, I0, J0, active, pa, pb, stage, step, step);
+  if (!active) return;
 
   // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
   const int kpad = (int)((a.n_f + 255) / 256 * 256);  // fields the fp4 loop covers
