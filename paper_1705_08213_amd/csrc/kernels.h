@@ -206,8 +206,12 @@ enum Path { kPathPopcount = 1, kPathMfma = 2 };
 
 // Kernel-shape table (tune.hip): kinds of launch, and the variant the table
 // picks for a problem of n_v vectors over n_f fields (0 .. n_variants - 1).
-enum TuneKind { kTuneManyMfma = 0, kTuneManyPopcount = 1 };
-int tune_pick(int kind, int64_t n_v, int64_t n_f, int n_variants);
+enum TuneKind { kTuneManyMfma = 0, kTuneManyPopcount = 1, kTuneOneShot = 2 };
+struct TuneChoice {
+  int variant;    // tile variant, in [0, n_variants)
+  int wg_per_cu;  // persistent workgroups per compute unit; 0: the launcher's default
+};
+TuneChoice tune_pick(int kind, int64_t n_v, int64_t n_f, int n_variants);
 
 // Optional event timing around the main kernel of a launcher (no-ops unless
 // enabled through ccc_timing_enable).

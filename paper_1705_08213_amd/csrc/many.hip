@@ -14,15 +14,18 @@
 //      wave per row), and the persistent work counter reset to 0 (a kernel
 //      store, so graphs hold no memset node);
 //   2. many_*_kernel, one persistent launch per tile variant in the batch: a
-//      grid of up to 2 workgroups per compute unit; each workgroup takes the
-//      next item of its variant's list with an atomic on that list's counter
-//      and computes the tile with the same device code as the one-shot
-//      kernels (tile2.h), until the list is exhausted.  Two variants run on
-//      forked graph branches, concurrently.
+//      grid of a few workgroups per compute unit (the tune table's figure
+//      for the variant's problems, else 2); each workgroup takes the next
+//      item of its variant's list with an atomic on that list's counter and
+//      computes the tile with the same device code as the one-shot kernels
+//      (tile2.h), until the list is exhausted.  The variants run on forked
+//      graph branches, concurrently.
 //
-// Tile variants (mfma path): 0 = 128 x 64 workgroup tiles (waves 64 x 32),
-// 1 = 64 x 32 workgroup tiles (waves 32 x 16).  The popcount path has one
-// shape (64 x 64).
+// Tile variants (mfma path), workgroup tile (wave tile): 0 = 128 x 64
+// (64 x 32), 1 = 64 x 32 (32 x 16), 2 = 64 x 64 (32 x 32), 3 = 32 x 32
+// (16 x 16).  A triangle is cut into squares of the workgroup tile's height,
+// each one or two workgroup tiles.  The popcount path has one shape
+// (64 x 64).
 #include <dlfcn.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -57,8 +60,16 @@ struct WorkItem {
   int32_t tile;  // index into the problem's halves-of-squares triangle enumeration
 };
 
-constexpr int kVariants = 2;
-constexpr int kSquare[kVariants] = {128, 64};  // square tile side per mfma variant
+constexpr int kVariants = 4;
+// wave tiles in 16-row blocks per mfma variant, and what follows from them
+constexpr int kWM[kVariants] = {4, 2, 2, 1}, kWN[kVariants] = {2, 1, 2, 1};
+constexpr int kSquare[kVariants] = {32 * kWM[0], 32 * kWM[1], 32 * kWM[2], 32 * kWM[3]};
+constexpr int kHalves[kVariants] = {kWM[0] / kWN[0], kWM[1] / kWN[1], kWM[2] / kWN[2],
+                                    kWM[3] / kWN[3]};  // workgroup tiles per square
+// workgroups per compute unit each variant's kernel is built for (its
+// register budget), the most a launch may ask
+constexpr int kMaxWg[kVariants] = {2, 4, 2, 4};
+constexpr int kDefaultWg = 2;
 constexpr int kPopTile = 64;
 
 // ---------------------------------------------------------------------------
@@ -117,11 +128,12 @@ __device__ __forceinline__ int next_item(unsigned* counter, int* slot) {
 template <int WM, int WN, bool F4>
 __device__ __forceinline__ void mfma_item(const Pair2Args& a, int64_t tiles_side, int tile,
                                           u4 (*stage)[2 * WM + 2 * WN][64]) {
-  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int BM = 32 * WM, BN = 32 * WN, HALVES = WM / WN;
+  static_assert(BM == HALVES * BN, "a square is whole workgroup tiles");
   const int wave = threadIdx.x >> 6;
   int64_t sq_i, sq_j;
-  tri_tile(tile >> 1, tiles_side, sq_i, sq_j);
-  const int64_t I = sq_i, J = 2 * sq_j + (tile & 1);
+  tri_tile(tile / HALVES, tiles_side, sq_i, sq_j);
+  const int64_t I = sq_i, J = HALVES * sq_j + tile % HALVES;
   tile2::mfma2_wave_tile<WM, WN, F4>(a, I * BM + (wave & 1) * 16 * WM,
                                      J * BN + (wave >> 1) * 16 * WN, stage);
 }
@@ -130,8 +142,8 @@ __device__ __forceinline__ void mfma_item(const Pair2Args& a, int64_t tiles_side
 // items form their own list and counter), so every kernel keeps the register
 // budget of its own tile shape.  F4: fp4 operands (every problem of the batch
 // has n_f <= kF4MaxFields), else int8.
-template <int WM, int WN, bool F4>
-__global__ __launch_bounds__(256, 2) void many_mfma_kernel(const ProbDesc* __restrict__ d,
+template <int WM, int WN, bool F4, int MIN_WG>
+__global__ __launch_bounds__(256, MIN_WG) void many_mfma_kernel(const ProbDesc* __restrict__ d,
                                                            const WorkItem* __restrict__ items,
                                                            int n_items,
                                                            unsigned* __restrict__ counter,
@@ -164,8 +176,9 @@ __global__ __launch_bounds__(256) void many_pop_kernel(const ProbDesc* __restric
   }
 }
 
-// Tile variant of a problem from the kernel-shape table (tune.hip).
-int pick_variant(int64_t n_v, int64_t n_f, int path) {
+// Tile variant and workgroups per CU of a problem from the kernel-shape
+// table (tune.hip).
+TuneChoice pick_variant(int64_t n_v, int64_t n_f, int path) {
   return tune_pick(path == CCC_PATH_POPCOUNT ? kTuneManyPopcount : kTuneManyMfma, n_v, n_f,
                    kVariants);
 }
@@ -185,14 +198,15 @@ struct Entry {
   WorkItem* items = nullptr;      // per-variant lists, back to back
   unsigned* counters = nullptr;   // one per variant
   int n_probs = 0;
-  int item_begin[kVariants] = {0, 0}, n_items[kVariants] = {0, 0};
+  int item_begin[kVariants] = {}, n_items[kVariants] = {};
   int64_t total_rows = 0;
   int path = 0;
   bool f4 = true;                 // fp4 operands (every n_f <= kF4MaxFields), else int8
   double gamma = 0;
-  int grid[kVariants] = {0, 0};
-  hipStream_t fork = nullptr;     // second capture stream for a concurrent variant
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int grid[kVariants] = {};
+  // capture streams of the variants after the first (concurrent branches)
+  hipStream_t fork[kVariants] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kVariants] = {};
 };
 
 std::mutex g_mu;
@@ -203,9 +217,11 @@ constexpr size_t kMaxEntries = 8;
 void destroy(Entry* e) {
   if (e->exec) (void)hipGraphExecDestroy(e->exec);
   if (e->capture) (void)hipStreamDestroy(e->capture);
-  if (e->fork) (void)hipStreamDestroy(e->fork);
+  for (int v = 0; v < kVariants; ++v) {
+    if (e->fork[v]) (void)hipStreamDestroy(e->fork[v]);
+    if (e->ev_join[v]) (void)hipEventDestroy(e->ev_join[v]);
+  }
   if (e->ev_fork) (void)hipEventDestroy(e->ev_fork);
-  if (e->ev_join) (void)hipEventDestroy(e->ev_join);
   if (e->dbuf) (void)hipFree(e->dbuf);
   delete e;
 }
@@ -224,11 +240,13 @@ std::vector<unsigned char> make_key(const ccc_problem* probs, int n, const ccc_o
   (void)hipGetDevice(&dev);
   memcpy(k.data() + off, &dev, sizeof(int));
   off += sizeof(int);
-  // variants can be forced from the environment; make them part of the key
-  const char* env = getenv("CCC_MANY_VARIANT");
-  int forced = env ? atoi(env) + 1 : 0;
-  memcpy(k.data() + off, &forced, sizeof(int));
-  off += sizeof(int);
+  // the choices can be forced from the environment; make them part of the key
+  for (const char* name : {"CCC_MANY_VARIANT", "CCC_MANY_WG"}) {
+    const char* env = getenv(name);
+    const int forced = env ? atoi(env) + 1 : 0;
+    memcpy(k.data() + off, &forced, sizeof(int));
+    off += sizeof(int);
+  }
   const int operands = f4 ? 4 : 8;
   memcpy(k.data() + off, &operands, sizeof(int));
   off += sizeof(int);
@@ -236,45 +254,58 @@ std::vector<unsigned char> make_key(const ccc_problem* probs, int n, const ccc_o
   return k;
 }
 
+template <int V, bool F4>
+void launch_mfma(const Entry& e, const WorkItem* items, hipStream_t stream) {
+  hipLaunchKernelGGL((many_mfma_kernel<kWM[V], kWN[V], F4, kMaxWg[V]>), dim3(e.grid[V]),
+                     dim3(256), 0, stream, e.d, items, e.n_items[V], e.counters + V, e.gamma);
+}
+
 hipError_t launch_variant(const Entry& e, int v, hipStream_t stream) {
   const WorkItem* items = e.items + e.item_begin[v];
-  if (e.path == CCC_PATH_POPCOUNT)
+  if (e.path == CCC_PATH_POPCOUNT) {
     hipLaunchKernelGGL(many_pop_kernel, dim3(e.grid[v]), dim3(256), 0, stream, e.d, items,
                        e.n_items[v], e.counters + v, e.gamma);
-  else if (v == 0 && e.f4)
-    hipLaunchKernelGGL((many_mfma_kernel<4, 2, true>), dim3(e.grid[v]), dim3(256), 0, stream, e.d,
-                       items, e.n_items[v], e.counters + v, e.gamma);
-  else if (v == 0)
-    hipLaunchKernelGGL((many_mfma_kernel<4, 2, false>), dim3(e.grid[v]), dim3(256), 0, stream,
-                       e.d, items, e.n_items[v], e.counters + v, e.gamma);
-  else if (e.f4)
-    hipLaunchKernelGGL((many_mfma_kernel<2, 1, true>), dim3(e.grid[v]), dim3(256), 0, stream, e.d,
-                       items, e.n_items[v], e.counters + v, e.gamma);
-  else
-    hipLaunchKernelGGL((many_mfma_kernel<2, 1, false>), dim3(e.grid[v]), dim3(256), 0, stream,
-                       e.d, items, e.n_items[v], e.counters + v, e.gamma);
+    return hipGetLastError();
+  }
+  switch (v * 2 + (e.f4 ? 1 : 0)) {
+    case 0: launch_mfma<0, false>(e, items, stream); break;
+    case 1: launch_mfma<0, true>(e, items, stream); break;
+    case 2: launch_mfma<1, false>(e, items, stream); break;
+    case 3: launch_mfma<1, true>(e, items, stream); break;
+    case 4: launch_mfma<2, false>(e, items, stream); break;
+    case 5: launch_mfma<2, true>(e, items, stream); break;
+    case 6: launch_mfma<3, false>(e, items, stream); break;
+    default: launch_mfma<3, true>(e, items, stream); break;
+  }
   return hipGetLastError();
 }
 
-// The batch's launches.  With `fork` (graph capture), a second variant runs
-// on a forked stream joined back before the end, so both variants' kernels
-// can share the GPU.
+// The batch's launches.  With `fork` (graph capture), every variant after
+// the first non-empty one runs on a forked stream joined back before the
+// end, so the variants' kernels can share the GPU.
 hipError_t enqueue(const Entry& e, hipStream_t stream, bool fork) {
   hipLaunchKernelGGL(count_many_kernel, dim3((unsigned)((e.total_rows + 3) / 4)), dim3(256), 0,
                      stream, e.d, e.n_probs, e.total_rows, e.counters);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const bool both = e.n_items[0] > 0 && e.n_items[1] > 0;
-  if (both && fork) {
-    if ((err = hipEventRecord(e.ev_fork, stream)) != hipSuccess) return err;
-    if ((err = hipStreamWaitEvent(e.fork, e.ev_fork, 0)) != hipSuccess) return err;
-    if ((err = launch_variant(e, 1, e.fork)) != hipSuccess) return err;
-    if ((err = hipEventRecord(e.ev_join, e.fork)) != hipSuccess) return err;
-    if ((err = launch_variant(e, 0, stream)) != hipSuccess) return err;
-    return hipStreamWaitEvent(stream, e.ev_join, 0);
+  int first = -1, forked = 0;
+  for (int v = 0; v < kVariants; ++v) {
+    if (e.n_items[v] == 0) continue;
+    if (first < 0 || !fork) {
+      if (first < 0) first = v;
+      if (!fork && (err = launch_variant(e, v, stream)) != hipSuccess) return err;
+      continue;
+    }
+    if (forked++ == 0 && (err = hipEventRecord(e.ev_fork, stream)) != hipSuccess) return err;
+    if ((err = hipStreamWaitEvent(e.fork[v], e.ev_fork, 0)) != hipSuccess) return err;
+    if ((err = launch_variant(e, v, e.fork[v])) != hipSuccess) return err;
+    if ((err = hipEventRecord(e.ev_join[v], e.fork[v])) != hipSuccess) return err;
   }
-  for (int v = 0; v < kVariants; ++v)
-    if (e.n_items[v] > 0 && (err = launch_variant(e, v, stream)) != hipSuccess) return err;
+  if (!fork || first < 0) return hipSuccess;
+  if ((err = launch_variant(e, first, stream)) != hipSuccess) return err;
+  for (int v = first + 1; v < kVariants; ++v)
+    if (e.n_items[v] > 0 && (err = hipStreamWaitEvent(stream, e.ev_join[v], 0)) != hipSuccess)
+      return err;
   return hipSuccess;
 }
 
@@ -284,6 +315,7 @@ int build_entry(const ccc_problem* probs, int n, const ccc_opts& o, bool f4, Ent
   std::vector<ProbDesc> d(n);
   std::vector<WorkItem> items[kVariants];
   std::vector<int64_t> cost[kVariants];
+  int wg[kVariants] = {};  // largest workgroups-per-CU figure among each variant's problems
   int64_t rows = 0, scratch_counts = 0;
   for (int p = 0; p < n; ++p) {
     const ccc_problem& q = probs[p];
@@ -296,17 +328,21 @@ int build_entry(const ccc_problem* probs, int n, const ccc_opts& o, bool f4, Ent
     x.ccc = q.ccc;
     x.counts = q.counts;
     x.row_begin = rows;
-    x.variant = o.path == CCC_PATH_POPCOUNT ? 0 : pick_variant(q.n_v, q.n_f, CCC_PATH_MFMA);
-    const int side = o.path == CCC_PATH_POPCOUNT ? kPopTile : kSquare[x.variant];
+    const bool pop = o.path == CCC_PATH_POPCOUNT;
+    const TuneChoice tc = pick_variant(q.n_v, q.n_f, pop ? CCC_PATH_POPCOUNT : CCC_PATH_MFMA);
+    x.variant = pop ? 0 : tc.variant;
+    const int side = pop ? kPopTile : kSquare[x.variant];
+    const int halves = pop ? 1 : kHalves[x.variant];
     const int64_t T = (q.n_v + side - 1) / side;
-    if (T > 46000) return CCC_ERR_ARG;  // item indices must fit int32
+    if (T > 65536 || halves * (T * (T + 1) / 2) > 0x7FFFFFFF)
+      return CCC_ERR_ARG;  // item indices must fit int32
     x.tiles_side = (int32_t)T;
     rows += q.n_v;
     if (!q.counts) scratch_counts += q.n_v;
     if (q.n_v < 2) continue;
-    const int64_t ntiles = o.path == CCC_PATH_POPCOUNT ? T * (T + 1) / 2 : T * (T + 1);
-    const int64_t tile_pairs = o.path == CCC_PATH_POPCOUNT ? (int64_t)side * side
-                                                            : (int64_t)side * side / 2;
+    wg[x.variant] = std::max(wg[x.variant], tc.wg_per_cu);
+    const int64_t ntiles = halves * (T * (T + 1) / 2);
+    const int64_t tile_pairs = (int64_t)side * side / halves;
     for (int64_t t = 0; t < ntiles; ++t) {
       items[x.variant].push_back(WorkItem{p, (int32_t)t});
       cost[x.variant].push_back(tile_pairs * (q.n_f + 256));
@@ -354,9 +390,12 @@ int build_entry(const ccc_problem* probs, int n, const ccc_opts& o, bool f4, Ent
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t want = (int64_t)cus * 2;
-  for (int v = 0; v < kVariants; ++v)
-    e->grid[v] = (int)std::max<int64_t>(1, std::min<int64_t>(want, e->n_items[v]));
+  for (int v = 0; v < kVariants; ++v) {
+    const int per_cu = std::min(wg[v] > 0 ? wg[v] : kDefaultWg,
+                                e->path == CCC_PATH_POPCOUNT ? kDefaultWg : kMaxWg[v]);
+    e->grid[v] = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu,
+                                                             e->n_items[v]));
+  }
   return CCC_OK;
 }
 
@@ -397,10 +436,11 @@ int run_many(const ccc_problem* probs, int n_probs, const ccc_opts& opts, bool f
     if (use_graph) {
       hipGraph_t graph = nullptr;
       bool ok = hipStreamCreateWithFlags(&e->capture, hipStreamNonBlocking) == hipSuccess &&
-                hipStreamCreateWithFlags(&e->fork, hipStreamNonBlocking) == hipSuccess &&
-                hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming) == hipSuccess &&
-                hipEventCreateWithFlags(&e->ev_join, hipEventDisableTiming) == hipSuccess &&
-                hipStreamBeginCapture(e->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming) == hipSuccess;
+      for (int v = 0; v < kVariants && ok; ++v)
+        ok = hipStreamCreateWithFlags(&e->fork[v], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&e->ev_join[v], hipEventDisableTiming) == hipSuccess;
+      ok = ok && hipStreamBeginCapture(e->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
         hipError_t le = enqueue(*e, e->capture, true);
         ok = hipStreamEndCapture(e->capture, &graph) == hipSuccess && le == hipSuccess &&

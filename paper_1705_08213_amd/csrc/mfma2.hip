@@ -60,28 +60,34 @@ __global__ __launch_bounds__(256, 2) void mfma2_complete_kernel(Pair2Args a,
                                               J * BN + (wave >> 1) * 16 * WN, stage, outs[wave]);
 }
 
-template <int WM, int WN, bool F4>
-__global__ __launch_bounds__(256, 2) void mfma2_kernel(Pair2Args a, int64_t tiles_side,
-                                                       int64_t tiles_n) {
+// The general kernel: 2 x 2 waves of (16 WM) x (16 WN) pairs.  Workgroups
+// of the 128 x 64 shape whose rows are all complete compute their tile
+// together in the one-plane form (mfma2_coop_complete).
+template <int WM, int WN, bool F4, int MIN_WG>
+__global__ __launch_bounds__(256, MIN_WG) void mfma2_kernel(Pair2Args a, int64_t tiles_side,
+                                                            int64_t tiles_n) {
   if (a.complete && *a.complete) return;  // uniform: mfma2_complete_kernel covers the call
-  constexpr int BM = 32 * WM, BN = 32 * WN;
-  static_assert(BM == 2 * BN, "triangle split assumes BM = 2 BN");
+  constexpr int BM = 32 * WM, BN = 32 * WN, NB = 2 * WM + 2 * WN;
+  constexpr bool kCoop = WM == 4 && WN == 2;
   const int wave = threadIdx.x >> 6;
   // XCD-contiguous runs of tiles (triangle: in strip order, so that a run
   // shares row and column blocks in one L2)
   int64_t I, J;
   tile_of<BM, BN>(a, xcd_unit(blockIdx.x, gridDim.x), tiles_side, tiles_n, I, J);
-  // 64 KB: the complete-data form's partial tiles, or else the workgroup's
-  // two fp4 stage buffers of 2 WM + 2 WN row blocks
-  __shared__ v4i part[4][16][64];
-  static_assert(sizeof(part) >= 2 * (2 * WM + 2 * WN) * 64 * sizeof(u4), "stage buffers fit");
-  if (tile2::workgroup_complete<WM, WN>(a, I * BM, J * BN)) {
-    tile2::mfma2_coop_complete<WM, WN, F4>(a, I * BM, J * BN, part);
-    return;
+  // the cooperative form's partial tiles (64 KB), or else the workgroup's
+  // two stage buffers of NB row blocks
+  __shared__ u4 smem[kCoop ? 4 * 16 * 64 : 2 * NB * 64];
+  static_assert(sizeof(smem) >= 2 * NB * 64 * sizeof(u4), "stage buffers fit");
+  if constexpr (kCoop) {
+    if (tile2::workgroup_complete<WM, WN>(a, I * BM, J * BN)) {
+      tile2::mfma2_coop_complete<WM, WN, F4>(a, I * BM, J * BN,
+                                             reinterpret_cast<v4i(*)[16][64]>(smem));
+      return;
+    }
   }
-  tile2::mfma2_wave_tile<WM, WN, F4>(
-      a, I * BM + (wave & 1) * 16 * WM, J * BN + (wave >> 1) * 16 * WN,
-      reinterpret_cast<u4(*)[2 * WM + 2 * WN][64]>(&part[0][0][0]));
+  tile2::mfma2_wave_tile<WM, WN, F4>(a, I * BM + (wave & 1) * 16 * WM,
+                                     J * BN + (wave >> 1) * 16 * WN,
+                                     reinterpret_cast<u4(*)[NB][64]>(smem));
 }
 
 // Grid of BM x BN workgroup tiles: tiles along a side (rows, columns) and
@@ -96,15 +102,31 @@ int64_t tile_grid(const Pair2Args& a, int64_t& tm, int64_t& tn) {
   return BM / BN * (s1 * tm - s1 * (s1 - 1) / 2 - (s0 * tm - s0 * (s0 - 1) / 2));
 }
 
-template <int WM, int WN, bool F4>
+template <int WM, int WN, bool F4, int MIN_WG>
 hipError_t launch_shape(const Pair2Args& a, hipStream_t stream) {
   int64_t tm, tn;
   const int64_t ntiles = tile_grid<32 * WM, 32 * WN>(a, tm, tn);
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((mfma2_kernel<WM, WN, F4>), dim3((unsigned)ntiles), dim3(256), 0, stream, a,
-                     tm, tn);
+  hipLaunchKernelGGL((mfma2_kernel<WM, WN, F4, MIN_WG>), dim3((unsigned)ntiles), dim3(256), 0,
+                     stream, a, tm, tn);
   return hipGetLastError();
+}
+
+// Shapes of the general kernel, picked per call by the kernel-shape table
+// (kind oneshot): 0 = 128 x 64 workgroup tiles (waves 64 x 32), 1 = 64 x 32
+// (32 x 16), 2 = 64 x 64 (32 x 32).  Smaller tiles give small calls more
+// workgroups.
+constexpr int kOneShotVariants = 3;
+
+template <bool F4>
+hipError_t launch_general(const Pair2Args& a, hipStream_t stream) {
+  const int64_t n = a.n_a > a.n_b ? a.n_a : a.n_b;
+  switch (tune_pick(kTuneOneShot, n, a.n_f, kOneShotVariants).variant) {
+    case 1: return launch_shape<2, 1, F4, 4>(a, stream);
+    case 2: return launch_shape<2, 2, F4, 2>(a, stream);
+    default: return launch_shape<4, 2, F4, 2>(a, stream);
+  }
 }
 
 // The complete-data kernel's wave tile: 128 x 64 pairs (8 x 4 blocks of 16).
@@ -132,7 +154,7 @@ hipError_t launch_f(const Pair2Args& a, hipStream_t stream) {
     if (e != hipSuccess) return e;
     if ((e = launch_complete<F4>(a, stream)) != hipSuccess) return e;
   }
-  return launch_shape<4, 2, F4>(a, stream);
+  return launch_general<F4>(a, stream);
 }
 
 }  // namespace

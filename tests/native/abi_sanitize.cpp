@@ -205,7 +205,9 @@ int main() {
   const char* tune = "/tmp/ccc_abi_sanitize_tune.txt";
   if (FILE* f = fopen(tune, "w")) {
     fputs("# comment\n\n garbage line\n1024 100000 mfma 1\n999999999999999999999 5 mfma 0\n"
-          "512 2 popcount 9\n-5 -5 mfma -1\n4096 60000 mfma 0\n7 7 bogus 1\n", f);
+          "512 2 popcount 9\n-5 -5 mfma -1\n4096 60000 mfma 0\n7 7 bogus 1\n"
+          "2048 4096 mfma 2 3\n8192 100 mfma 3 999\n100 100 oneshot 1\n5000 5000 oneshot 7\n",
+          f);
     fclose(f);
     setenv("CCC_TUNE_FILE", tune, 1);
   }

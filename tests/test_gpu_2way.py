@@ -8,8 +8,8 @@ import oracle
 import oracle.brute
 import paper_1705_08213_amd as ccc
 import synth
-from gpu_util import (FORMS, assert_ccc_close, assert_ccc_identical, assert_tables_equal, dev,
-                      form_kw, host, say)
+from gpu_util import (FORMS, MFMA_FORMS, assert_ccc_close, assert_ccc_identical,
+                      assert_tables_equal, dev, form_kw, host, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -147,3 +147,48 @@ def test_2way_ccc_bit_identical_to_oracle(path, missing):
     _, c, _ = run2(v, 2500, path)
     _, oc = oracle.two_way(v, 2500)
     assert_ccc_identical(c, oc)
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2"])
+@pytest.mark.parametrize("form", MFMA_FORMS)
+def test_2way_oneshot_tile_variants(variant, form, monkeypatch):
+    """Every workgroup-tile shape of the one-shot general kernel, forced (the
+    kernel-shape table picks among them by size): ragged triangles, a row
+    range, a block, and complete data with one missing entry (complete tiles
+    inside a call that is not complete)."""
+    import torch
+    monkeypatch.setenv("CCC_ONESHOT_VARIANT", variant)
+    for n_v, n_f in [(300, 1537), (97, 300)]:
+        say("2way variant", variant, form, n_v, n_f)
+        v = synth.beta_hw(n_v, n_f, seed=1300 + n_v, missing=0.02)
+        t, c, _ = run2(v, n_f, form)
+        ot, oc = oracle.two_way(v, n_f)
+        assert_tables_equal(t, ot)
+        assert_ccc_close(c, oc)
+        t, c, _ = ccc.ccc_2way_rows(dev(v), n_f, 37, 70, **form_kw(form))
+        torch.cuda.synchronize()
+        ot, oc = oracle.two_way(v, n_f, 37, 70)
+        assert_tables_equal(host(t), ot)
+        assert_ccc_close(host(c), oc)
+    say("2way variant block", variant, form)
+    n_a, n_b, n_f = 150, 70, 999
+    va = synth.beta_hw(n_a, n_f, seed=1401, missing=0.02)
+    vb = synth.beta_hw(n_b, n_f, seed=1402, missing=0.02)
+    tables = torch.empty((n_a, n_b, 4), dtype=torch.int32, device="cuda")
+    ca = torch.empty((n_a, 4), dtype=torch.int32, device="cuda")
+    cb = torch.empty((n_b, 4), dtype=torch.int32, device="cuda")
+    cc = torch.empty((n_a, n_b, 4), dtype=torch.float64, device="cuda")
+    ccc.ccc_2way_block(dev(va), dev(vb), n_f, tables, ca, cb, cc, **form_kw(form))
+    torch.cuda.synchronize()
+    ot, oc = oracle.block(va, vb, n_f)
+    assert_tables_equal(host(tables), ot)
+    assert_ccc_close(host(cc), oc)
+    say("2way variant mixed complete", variant, form)
+    n_v, n_f = 260, 700
+    codes = oracle.brute.unpack_codes(synth.beta_hw(n_v, n_f, seed=1403, missing=0.0), n_f)
+    codes[200, 345] = 2  # one missing entry: the call is not complete
+    v = synth.pack_codes(codes, pad_value=-1)
+    t, c, _ = run2(v, n_f, form)
+    ot, oc = oracle.two_way(v, n_f)
+    assert_tables_equal(t, ot)
+    assert_ccc_close(c, oc)

@@ -33,12 +33,17 @@ SIZES = [(300, 1000), (2, 5), (1, 77), (129, 4097), (64, 256), (700, 333), (5, 0
          (1000, 2000), (3, 64)]
 
 
-@pytest.fixture(params=["0", "1", "tuned"])
+# every tile variant of the persistent kernels (forced), one with a forced
+# workgroups-per-CU figure, and the tuned choice
+@pytest.fixture(params=["0", "1", "2", "3", "1/wg1", "tuned"])
 def variant(request, monkeypatch):
+    monkeypatch.delenv("CCC_MANY_VARIANT", raising=False)
+    monkeypatch.delenv("CCC_MANY_WG", raising=False)
     if request.param != "tuned":
-        monkeypatch.setenv("CCC_MANY_VARIANT", request.param)
-    else:
-        monkeypatch.delenv("CCC_MANY_VARIANT", raising=False)
+        var, _, wg = request.param.partition("/wg")
+        monkeypatch.setenv("CCC_MANY_VARIANT", var)
+        if wg:
+            monkeypatch.setenv("CCC_MANY_WG", wg)
     yield request.param
 
 
