@@ -246,9 +246,7 @@ __global__ void unit_offsets_kernel(UnitGrid g, int64_t* __restrict__ offs) {
   int64_t s = 0, it = 0, kt = 0;
   if (lo < hi) pair_tiles(g, lo, it, kt);
   for (int64_t p = lo; p < hi; ++p) {
-    int64_t jlo, jhi;
-    pair_j_range(g, it, kt, jlo, jhi);
-    s += jhi - jlo;
+    s += pair_units(g, it, kt);
     if (++kt == g.nt) kt = ++it;
   }
   part[t] = s;
@@ -266,9 +264,7 @@ __global__ void unit_offsets_kernel(UnitGrid g, int64_t* __restrict__ offs) {
   if (lo < hi) pair_tiles(g, lo, it, kt);
   for (int64_t p = lo; p < hi; ++p) {
     offs[p] = run;
-    int64_t jlo, jhi;
-    pair_j_range(g, it, kt, jlo, jhi);
-    run += jhi - jlo;
+    run += pair_units(g, it, kt);
     if (++kt == g.nt) kt = ++it;
   }
   if (t == 1023) offs[P] = run;
@@ -278,35 +274,33 @@ __global__ void unit_offsets_kernel(UnitGrid g, int64_t* __restrict__ offs) {
 inline int64_t grid_units(const UnitGrid& g) {
   int64_t total = 0;
   for (int64_t it = g.it0; it < g.it1; ++it)
-    for (int64_t kt = it; kt < g.nt; ++kt) {
-      int64_t jlo, jhi;
-      pair_j_range(g, it, kt, jlo, jhi);
-      total += jhi - jlo;
-    }
+    for (int64_t kt = it; kt < g.nt; ++kt) total += pair_units(g, it, kt);
   return total;
 }
 
-// Launch a 3-way kernel over all its tetrahedral units of b x b tiles (256
-// threads each), in slices of at most 2^30 workgroups.  a.offs must hold
-// grid_pairs + 1 int64.
+// Launch a 3-way kernel over all its tetrahedral units of b x b tiles and
+// `run` middle vectors (256 threads each), in slices of at most 2^30
+// workgroups.  offs must hold grid_pairs + 1 int64; `name` (if any) opens a
+// timing mark around the launches.
 template <typename Kernel, typename Args>
 hipError_t launch_units(Kernel kernel, const Args& a, int64_t b, const char* name,
-                        hipStream_t stream) {
-  const UnitGrid g = unit_grid(a.n, b, a.i_begin, a.i_end);
+                        hipStream_t stream, int64_t run = 1, int64_t* offs = nullptr) {
+  if (!offs) offs = a.offs;
+  const UnitGrid g = unit_grid(a.n, b, a.i_begin, a.i_end, run);
   const int64_t total = grid_units(g);
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(unit_offsets_kernel, dim3(1), dim3(1024), 0, stream, g, a.offs);
+  hipLaunchKernelGGL(unit_offsets_kernel, dim3(1), dim3(1024), 0, stream, g, offs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t kMaxGrid = 0x40000000;
-  timing_begin(name, stream);
+  if (name) timing_begin(name, stream);
   for (int64_t base = 0; base < total; base += kMaxGrid) {
     int64_t cnt = total - base < kMaxGrid ? total - base : kMaxGrid;
     hipLaunchKernelGGL(kernel, dim3((unsigned)cnt), dim3(256), 0, stream, a, g,
-                       (const int64_t*)a.offs, base, cnt);
+                       (const int64_t*)offs, base, cnt);
     if ((e = hipGetLastError()) != hipSuccess) break;
   }
-  timing_end(stream);
+  if (name) timing_end(stream);
   return e;
 }
 

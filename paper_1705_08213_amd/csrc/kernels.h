@@ -58,22 +58,26 @@ constexpr int64_t kF4MaxFields = int64_t(1) << 22;
 constexpr int64_t kUnitTile = 64;
 
 // Tetrahedral work units of the 3-way kernels.  Rows are cut into b-row
-// tiles; a unit is (I tile it, K tile kt, middle vector j) with it <= kt and
-// covers every triple i < j < k with i in tile it (and in the staged range
-// [i_begin, i_end)) and k in tile kt.  Units are ordered by tile pair (it
-// major, then kt) and, within a pair, by j: consecutive units share both row
-// tiles, so a run of them on one XCD reads the tiles from its L2 once.
+// tiles; a unit is (I tile it, K tile kt, middle vectors j .. j + run - 1)
+// with it <= kt and covers every triple i < j < k with i in tile it (and in
+// the staged range [i_begin, i_end)) and k in tile kt, for its run of
+// consecutive middle vectors (cut from the pair's j range; the last run of
+// a pair may be shorter).  Units are ordered by tile pair (it major, then
+// kt) and, within a pair, by j: consecutive units share both row tiles, so
+// a run of them on one XCD reads the tiles from its L2 once.
 struct UnitGrid {
   int64_t n, b, i_begin, i_end;
   int64_t it0, it1;  // I tiles [it0, it1)
   int64_t nt;        // tiles of all n rows
+  int64_t run;       // middle vectors per unit
 };
 
 __host__ __device__ __forceinline__ UnitGrid unit_grid(int64_t n, int64_t b, int64_t i_begin,
-                                                       int64_t i_end) {
+                                                       int64_t i_end, int64_t run = 1) {
   UnitGrid g;
   g.n = n;
   g.b = b;
+  g.run = run;
   g.i_begin = i_begin;
   g.i_end = i_end;
   g.it0 = i_begin / b;
@@ -107,6 +111,14 @@ __host__ __device__ __forceinline__ void pair_j_range(const UnitGrid& g, int64_t
   if (jhi < jlo) jhi = jlo;
 }
 
+// Units of tile pair (it, kt): its j range in runs of g.run.
+__host__ __device__ __forceinline__ int64_t pair_units(const UnitGrid& g, int64_t it,
+                                                       int64_t kt) {
+  int64_t jlo, jhi;
+  pair_j_range(g, it, kt, jlo, jhi);
+  return (jhi - jlo + g.run - 1) / g.run;
+}
+
 // Tile pair of pair index p.
 __host__ __device__ __forceinline__ void pair_tiles(const UnitGrid& g, int64_t p, int64_t& it,
                                                     int64_t& kt) {
@@ -119,8 +131,8 @@ __host__ __device__ __forceinline__ void pair_tiles(const UnitGrid& g, int64_t p
   kt = it + (p - grid_row_start(g, it));
 }
 
-// Unit u -> (j, I tile, K tile), given offs[p] = units of all pairs before p
-// (p = 0..pairs).
+// Unit u -> (first middle vector j of its run, I tile, K tile), given
+// offs[p] = units of all pairs before p (p = 0..pairs).
 __host__ __device__ __forceinline__ void unit_coords(int64_t u, const UnitGrid& g,
                                                      const int64_t* __restrict__ offs,
                                                      int64_t& j, int64_t& it, int64_t& kt) {
@@ -132,7 +144,7 @@ __host__ __device__ __forceinline__ void unit_coords(int64_t u, const UnitGrid& 
   pair_tiles(g, lo, it, kt);
   int64_t jlo, jhi;
   pair_j_range(g, it, kt, jlo, jhi);
-  j = jlo + (u - offs[lo]);
+  j = jlo + g.run * (u - offs[lo]);
 }
 
 // Workgroup b of a grid of `count` -> unit index, so that the workgroups the
@@ -200,6 +212,12 @@ struct Triple3Args {
   // MFMA launcher; null turns the complete-data path off.
   int32_t* gram;
   int64_t g0, ng;
+  // Complete-data flag and the unit offsets of the run grid its kernel walks
+  // (fp4 MFMA with a Gram matrix only; null: every unit votes for itself).
+  // launch_mfma3 sets *complete to 1 when every row of [g0, n) has all n_f
+  // fields present.
+  int* complete;
+  int64_t* offs_run;
 };
 
 enum Path { kPathPopcount = 1, kPathMfma = 2 };

@@ -439,6 +439,68 @@ __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, in
     }
 }
 
+// The 16 triples a lane holds in one 16-row block of a complete-data tile:
+// rows ib + 4g + e (e = 0..3), columns k0 + 16c + rl (c = 0..3), middle
+// vector j.  xyz[c][e] is S_xyz (fp4: the sum modulated by D_j, to which
+// G[i][k] is added here); the pair sums come from the Gram matrix and the
+// single counts from the 1-way counts.  fp4: the dense output is staged
+// through `scratch` (384 x 16 bytes of this wave's LDS).
+template <bool F4>
+__device__ __forceinline__ void complete_block_row(const Triple3Args& a, int64_t j, int64_t ib,
+                                                   int64_t k0, const v4i (&xyz)[4],
+                                                   u4* scratch) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+  const int64_t n = a.n;
+  const v4i* cnt = reinterpret_cast<const v4i*>(a.counts);
+  const int64_t ng = a.ng, g0 = a.g0;
+  const unsigned S8 = 8u * (unsigned)a.n_f, Y = (unsigned)cnt[j].y;
+  const int32_t* grow_j = a.gram + (j - g0) * ng;
+  double wj[2], wk[4][2];
+  triple_factors(a, j, wj);
+  unsigned Z[4], YZ[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t k = k0 + 16 * c + rl;
+    const int64_t kk = k > j && k < n ? k : j;  // a valid row for invalid lanes
+    triple_factors(a, kk, wk[c]);
+    Z[c] = (unsigned)cnt[kk].y;
+    YZ[c] = (unsigned)grow_j[kk - g0];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = ib + 4 * g + e;
+    const int64_t ii = i < j ? i : j;  // a valid row for invalid lanes
+    double wi[2];
+    triple_factors(a, ii, wi);
+    const unsigned X = (unsigned)cnt[ii].y;
+    const int32_t* grow_i = a.gram + (ii - g0) * ng;
+    const unsigned XY = (unsigned)grow_i[j - g0];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t k = k0 + 16 * c + rl;
+      const bool valid = k > j && k < n && i < j;
+      const int64_t kk = k > j && k < n ? k : j;
+      const unsigned XZ = (unsigned)grow_i[kk - g0];
+      // fp4: the partial sums hold sum rho_i(1) D_j rho_k(1)
+      const unsigned XYZ = F4 ? XZ + (unsigned)xyz[c][e] : (unsigned)xyz[c][e];
+      int t[8];
+      t[7] = (int)XYZ;
+      t[6] = (int)(2u * XY - XYZ);
+      t[5] = (int)(2u * XZ - XYZ);
+      t[3] = (int)(2u * YZ[c] - XYZ);
+      t[4] = (int)(4u * X - 2u * XY - 2u * XZ + XYZ);
+      t[2] = (int)(4u * Y - 2u * XY - 2u * YZ[c] + XYZ);
+      t[1] = (int)(4u * Z[c] - 2u * XZ - 2u * YZ[c] + XYZ);
+      t[0] = (int)(S8 - 4u * (X + Y + Z[c]) + 2u * (XY + XZ + YZ[c]) - XYZ);
+      if constexpr (F4)
+        emit_triple_staged(a, valid, i, j, k, t, wi, wj, wk[c], scratch);
+      else
+        emit_triple(a, valid, i, j, k, t, wi, wj, wk[c]);
+    }
+  }
+}
+
 // Complete-data unit (see the notes at the top): all four waves build the
 // same 64 x 64 tile of S_xyz over a quarter of the 256-field super-steps
 // each, the partial sums meet in LDS, and wave w finishes rows 16w..16w+15.
@@ -596,62 +658,174 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
     }
   __syncthreads();
 
-  // Rows i0 + 16 wave + 4g + e, columns k0 + 16c + rl.
-  const v4i* cnt = reinterpret_cast<const v4i*>(a.counts);
-  const int64_t ng = a.ng, g0 = a.g0;
-  const unsigned S8 = 8u * (unsigned)a.n_f, Y = (unsigned)cnt[j].y;
-  const int32_t* grow_j = a.gram + (j - g0) * ng;
-  double wj[2], wk[4][2];
-  triple_factors(a, j, wj);
   v4i xyz[4];
-  unsigned Z[4], YZ[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     xyz[c] = part[0][4 * wave + c][lane] + part[1][4 * wave + c][lane] +
              part[2][4 * wave + c][lane] + part[3][4 * wave + c][lane];
   }
   if constexpr (F4) __syncthreads();  // every wave's sums are read: part[wave] stages its stores
+  complete_block_row<F4>(a, j, i0 + 16 * wave, k0, xyz, reinterpret_cast<u4*>(&part[wave][0][0]));
+}
+
+// Middle vectors per unit of the complete-data kernel: one per wave.
+constexpr int64_t kJRun = 4;
+
+// Complete-data kernel, for calls whose every row has all n_f fields present
+// (the flag set by complete3_flag_kernel picks it; it exits at once
+// otherwise).  A workgroup takes a run of kJRun consecutive middle vectors j
+// of one tile pair (I tile, K tile), one per wave, and each wave computes the
+// whole 64 x 64 (i, k) tile of S_xyz = G[i][k] + sum rho_i(1) D_j rho_k(1)
+// for its j over every field (4 x 4 blocks of one fp4 plane).  The unit's 4 i
+// blocks, 4 k blocks and its j rows (16 copies of one row each) travel
+// through the workgroup's LDS stage once per super-step for all four waves:
+// a quarter of the bytes from L2 per triple of the one-j unit
+// (complete_unit), and no partial sums to add.
+__global__ __launch_bounds__(256, 2) void mfma3_complete_kernel(Triple3Args a, UnitGrid ug,
+                                                                const int64_t* __restrict__ offs,
+                                                                int64_t unit_base,
+                                                                int64_t count) {
+#pragma clang fp contract(off)
+  if (*a.complete == 0) return;  // uniform
+  constexpr int NB = 8 + kJRun, BPW = NB / 4;  // row blocks per step, per wave
+  static_assert(NB % 4 == 0, "every wave copies the same number of blocks");
+  __shared__ u4 stage[2][NB][64];  // 24 KB
+  __shared__ u4 outs[4][384];      // 24 KB: each wave's store staging
+  const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
+  const int64_t n = a.n;
+  const int64_t u = unit_base + xcd_unit(blockIdx.x, count);
+  int64_t j0, it, kt, jlo, jhi;
+  unit_coords(u, ug, offs, j0, it, kt);
+  pair_j_range(ug, it, kt, jlo, jhi);
+  const int64_t jn = jhi - j0 < kJRun ? jhi - j0 : kJRun;  // middle vectors of this run
+  const int64_t j = j0 + (wave < jn ? wave : jn - 1);      // inactive waves repeat the last
+  const bool active = wave < jn;
+  const int64_t i0 = it * BI, k0 = kt * BK;
+
+  // Copies: blocks 0-3 rows i, 4-7 rows k, 8 + w the run's w-th j (16 copies
+  // of the row); a wave-uniform base (the block's first row, clamped) plus
+  // a 32-bit lane offset (r - rf < 16 rows of at most 2^28 bytes).
+  gbytes base[BPW];
+  uint32_t off[BPW];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int64_t k = k0 + 16 * c + rl;
-    const int64_t kk = k > j && k < n ? k : j;  // a valid row for invalid lanes
-    triple_factors(a, kk, wk[c]);
-    Z[c] = (unsigned)cnt[kk].y;
-    YZ[c] = (unsigned)grow_j[kk - g0];
+  for (int t = 0; t < BPW; ++t) {
+    const int b = BPW * wave + t;
+    int64_t r0, r1;
+    if (b < 8) {
+      r0 = (b < 4 ? i0 + 16 * b : k0 + 16 * (b - 4));
+      r1 = r0 + rl;
+    } else {
+      r0 = j0 + (b - 8 < jn ? b - 8 : jn - 1);
+      r1 = r0;
+    }
+    const int64_t rf = r0 < n ? r0 : n - 1, r = r1 < n ? r1 : n - 1;
+    const uint64_t bp = (uint64_t)(a.v + rf * a.ld);
+    base[t] = (gbytes)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
+    off[t] = (uint32_t)((r - rf) * a.ld + 16 * g);
   }
+  auto issue = [&](int64_t st, int buf) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t i = i0 + 16 * wave + 4 * g + e;
-    const int64_t ii = i < j ? i : j;  // a valid row for invalid lanes
-    double wi[2];
-    triple_factors(a, ii, wi);
-    const unsigned X = (unsigned)cnt[ii].y;
-    const int32_t* grow_i = a.gram + (ii - g0) * ng;
-    const unsigned XY = (unsigned)grow_i[j - g0];
+    for (int t = 0; t < BPW; ++t)
+      tile2::stage_row((const uint8_t*)(base[t] + st * 64 + off[t]),
+                       &stage[buf][BPW * wave + t][0]);
+  };
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[m][c] = v4f{0, 0, 0, 0};
+  // one super-step; `complete`: no padding code in the step's words
+  auto body = [&](const u4 (&xa)[4], const u4 (&xk)[4], const u4& xj, auto complete) {
+    auto rho1_pair = [&](unsigned w0, unsigned w1) {
+      if constexpr (complete.value)
+        return tile2::rho1_nibbles_complete(w0, w1);
+      else
+        return tile2::nibbles32(tile2::rho1_16_f4<false>(w0), tile2::rho1_16_f4<false>(w1));
+    };
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      unsigned y[4], sg[4];
+      j_masks_f4(word_of(xj, 2 * h), y, sg, nullptr);
+      j_masks_f4(word_of(xj, 2 * h + 1), y + 2, sg + 2, nullptr);
+      v8i A[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) A[m] = rho1_pair(word_of(xa[m], 2 * h), word_of(xa[m], 2 * h + 1));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const v8i R = rho1_pair(word_of(xk[c], 2 * h), word_of(xk[c], 2 * h + 1));
+        v8i B;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B[q] = (int)mod_d((unsigned)R[q], y[q], sg[q]);
+#pragma unroll
+        for (int q = 4; q < 8; ++q) B[q] = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m][c] = tile2::mfma_f4(A[m], B, acc[m][c]);
+      }
+    }
+  };
+
+  // Whole super-steps through the stage: one barrier per step (every block
+  // has landed; the buffer read one step earlier is free), the words read
+  // before the next copy is issued.  Then the padded last step from plain
+  // loads.
+  const int64_t nfull = a.n_f / 256;
+  if (nfull > 0) issue(0, 0);
+  for (int64_t st = 0; st < nfull; ++st) {
+    const int buf = (int)(st & 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's blocks have landed
+    __syncthreads();                                   // every wave's have; buf ^ 1 is free
+    u4 xa[4], xk[4], xj;
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) xa[m] = stage[buf][m][lane];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xk[c] = stage[buf][4 + c][lane];
+      xj = stage[buf][8 + wave][lane];
+    }
+    if (st + 1 < nfull) issue(st + 1, buf ^ 1);
+    if (active) body(xa, xk, xj, std::true_type{});
+  }
+  if (!active) return;
+  if (nfull * 256 < a.n_f) {
+    const int64_t kb = nfull * 64 + 16 * g;
+    u4 xa[4], xk[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      int64_t r = i0 + 16 * m + rl;
+      xa[m] = load_fields64(a.v + (r < n ? r : n - 1) * a.ld, kb, a.n_f);
+      r = k0 + 16 * m + rl;
+      xk[m] = load_fields64(a.v + (r < n ? r : n - 1) * a.ld, kb, a.n_f);
+    }
+    body(xa, xk, load_fields64(a.v + j * a.ld, kb, a.n_f), std::false_type{});
+  }
+
+  // Epilogue: 4 block rows of 16 triples per lane for this wave's j.
+  tile2::static_for<4>([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+    v4i xyz[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int64_t k = k0 + 16 * c + rl;
-      const bool valid = k > j && k < n && i < j;
-      const int64_t kk = k > j && k < n ? k : j;
-      const unsigned XZ = (unsigned)grow_i[kk - g0];
-      // fp4: the partial sums hold sum rho_i(1) D_j rho_k(1)
-      const unsigned XYZ = F4 ? XZ + (unsigned)xyz[c][e] : (unsigned)xyz[c][e];
-      int t[8];
-      t[7] = (int)XYZ;
-      t[6] = (int)(2u * XY - XYZ);
-      t[5] = (int)(2u * XZ - XYZ);
-      t[3] = (int)(2u * YZ[c] - XYZ);
-      t[4] = (int)(4u * X - 2u * XY - 2u * XZ + XYZ);
-      t[2] = (int)(4u * Y - 2u * XY - 2u * YZ[c] + XYZ);
-      t[1] = (int)(4u * Z[c] - 2u * XZ - 2u * YZ[c] + XYZ);
-      t[0] = (int)(S8 - 4u * (X + Y + Z[c]) + 2u * (XY + XZ + YZ[c]) - XYZ);
-      if constexpr (F4)
-        emit_triple_staged(a, valid, i, j, k, t, wi, wj, wk[c],
-                           reinterpret_cast<u4*>(&part[wave][0][0]));
-      else
-        emit_triple(a, valid, i, j, k, t, wi, wj, wk[c]);
+      const v4f x = acc[m][c];
+      xyz[c] = v4i{tile2::f4_count(x[0]), tile2::f4_count(x[1]), tile2::f4_count(x[2]),
+                   tile2::f4_count(x[3])};
     }
-  }
+    complete_block_row<true>(a, j, i0 + 16 * m, k0, xyz, outs[wave]);
+  });
+}
+
+// *flag = 1 if every row of [r0, n) has all n_f fields present (one
+// workgroup; its threads read the counts with a stride).
+__global__ __launch_bounds__(1024) void complete3_flag_kernel(const int32_t* __restrict__ counts,
+                                                              int64_t r0, int64_t n, int64_t n_f,
+                                                              int* __restrict__ flag) {
+  bool ok = n_f > 0;
+  for (int64_t r = r0 + threadIdx.x; r < n && ok; r += blockDim.x)
+    ok = reinterpret_cast<const v4i*>(counts)[r].z == n_f;
+  ok = __syncthreads_and(ok ? 1 : 0) != 0;
+  if (threadIdx.x == 0) *flag = ok ? 1 : 0;
 }
 
 template <bool F4>
@@ -664,6 +838,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid u
   __shared__ v4i part[4][16][64];
   static_assert(sizeof(part) >= (2 * (2 * WI + 2 * WK + 1) * 64 + 4 * 384) * sizeof(u4),
                 "stage buffers fit");
+  if (a.complete && *a.complete) return;  // uniform: mfma3_complete_kernel covers the call
   const int wave = threadIdx.x >> 6;
   const int64_t n = a.n;
   const int64_t u = unit_base + xcd_unit(blockIdx.x, count);
@@ -742,8 +917,20 @@ hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (a.f4) return launch_units(mfma3_kernel<true>, a, BI, "mfma3", stream);
-  return launch_units(mfma3_kernel<false>, a, BI, "mfma3", stream);
+  timing_begin("mfma3", stream);
+  hipError_t e = hipSuccess;
+  if (a.complete) {
+    // the flag, then both kernels: each exits at once unless the flag picks it
+    hipLaunchKernelGGL(complete3_flag_kernel, dim3(1), dim3(1024), 0, stream, a.counts, a.g0,
+                       a.n, a.n_f, a.complete);
+    if ((e = hipGetLastError()) == hipSuccess)
+      e = launch_units(mfma3_complete_kernel, a, BI, nullptr, stream, kJRun, a.offs_run);
+  }
+  if (e == hipSuccess)
+    e = a.f4 ? launch_units(mfma3_kernel<true>, a, BI, nullptr, stream)
+             : launch_units(mfma3_kernel<false>, a, BI, nullptr, stream);
+  timing_end(stream);
+  return e;
 }
 
 }  // namespace ccc

@@ -1,8 +1,9 @@
 // Host-side check of the 3-way work-unit enumeration (UnitGrid helpers of
-// the library's kernels.h, compiled for the host): for each case, the units
-// cover every triple i < j < k with i in [i_begin, min(i_end, n-2)) exactly
-// once, every unit lies inside its tile pair, and the XCD remap of a grid is
-// a permutation.  Also the 2-way strip order of squares (strip_square) is a
+// the library's kernels.h, compiled for the host): for each case and run
+// length (1 middle vector per unit, and the complete-data kernel's runs of
+// 4), the units cover every triple i < j < k with i in
+// [i_begin, min(i_end, n-2)) exactly once, every unit lies inside its tile
+// pair, and the XCD remap of a grid is a permutation.  Also the 2-way strip order of squares (strip_square) is a
 // one-to-one map onto each row range's squares.  Prints "ok <cases>" and
 // exits 0, or names the first failure.
 #include <stdio.h>
@@ -19,10 +20,10 @@ static int fail(const char* what, long n, long ib, long ie) {
   return 1;
 }
 
-static int check(int64_t n, int64_t ib, int64_t ie, int64_t b) {
+static int check(int64_t n, int64_t ib, int64_t ie, int64_t b, int64_t run) {
   const int64_t row_end = ie < n - 2 ? ie : n - 2;
   if (row_end <= ib) return 0;
-  const UnitGrid g = unit_grid(n, b, ib, row_end);
+  const UnitGrid g = unit_grid(n, b, ib, row_end, run);
   const int64_t P = grid_pairs(g);
   std::vector<int64_t> offs(P + 1, 0);
   for (int64_t p = 0; p < P; ++p) {
@@ -30,7 +31,8 @@ static int check(int64_t n, int64_t ib, int64_t ie, int64_t b) {
     pair_tiles(g, p, it, kt);
     if (it < g.it0 || it >= g.it1 || kt < it || kt >= g.nt) return fail("pair_tiles", n, ib, ie);
     pair_j_range(g, it, kt, jlo, jhi);
-    offs[p + 1] = offs[p] + (jhi - jlo);
+    offs[p + 1] = offs[p] + (jhi - jlo + run - 1) / run;
+    if (pair_units(g, it, kt) != offs[p + 1] - offs[p]) return fail("pair_units", n, ib, ie);
   }
   const int64_t U = offs[P];
   std::vector<unsigned char> seen(U, 0);
@@ -42,15 +44,17 @@ static int check(int64_t n, int64_t ib, int64_t ie, int64_t b) {
   // cover[i][j][k] as a flat count over the staged triples
   std::vector<unsigned char> cover((size_t)n * n * n, 0);
   for (int64_t u = 0; u < U; ++u) {
-    int64_t j, it, kt, jlo, jhi;
-    unit_coords(u, g, offs.data(), j, it, kt);
+    int64_t j0, it, kt, jlo, jhi;
+    unit_coords(u, g, offs.data(), j0, it, kt);
     pair_j_range(g, it, kt, jlo, jhi);
-    if (j < jlo || j >= jhi || j < 1 || j > n - 2) return fail("unit_coords", n, ib, ie);
-    for (int64_t i = it * b; i < (it + 1) * b && i < j; ++i) {
-      if (i < ib || i >= row_end) continue;
-      for (int64_t k = kt * b; k < (kt + 1) * b && k < n; ++k)
-        if (k > j) ++cover[((size_t)i * n + j) * n + k];
-    }
+    if (j0 < jlo || j0 >= jhi || j0 < 1 || j0 > n - 2 || (j0 - jlo) % run)
+      return fail("unit_coords", n, ib, ie);
+    for (int64_t j = j0; j < j0 + run && j < jhi; ++j)
+      for (int64_t i = it * b; i < (it + 1) * b && i < j; ++i) {
+        if (i < ib || i >= row_end) continue;
+        for (int64_t k = kt * b; k < (kt + 1) * b && k < n; ++k)
+          if (k > j) ++cover[((size_t)i * n + j) * n + k];
+      }
   }
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = i + 1; j < n; ++j)
@@ -85,15 +89,16 @@ int main() {
                            {150, 64, 70},  {150, 70, 129}, {150, 129, 150}, {90, 0, 5},
                            {90, 88, 90},   {200, 63, 65},  {200, 127, 128}, {197, 0, 197}};
   int count = 0;
-  for (const auto& c : cases) {
-    if (check(c[0], c[1], c[2], 64)) return 1;
-    ++count;
-  }
+  for (int64_t run : {1, 4})
+    for (const auto& c : cases) {
+      if (check(c[0], c[1], c[2], 64, run)) return 1;
+      ++count;
+    }
   srand(7);
-  for (int r = 0; r < 30; ++r) {
+  for (int r = 0; r < 40; ++r) {
     const long n = 3 + rand() % 180, ib = rand() % (n + 1), ie = ib + rand() % (n + 1 - ib);
     const long b = (r & 1) ? 64 : 16;
-    if (check(n, ib, ie, b)) return 1;
+    if (check(n, ib, ie, b, (r & 2) ? 4 : 1)) return 1;
     ++count;
   }
   for (int64_t T = 1; T <= 40; ++T)  // every row range of small triangles
