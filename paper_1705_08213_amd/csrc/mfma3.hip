@@ -681,7 +681,7 @@ constexpr int64_t kJRun = 4;
 // through the workgroup's LDS stage once per super-step for all four waves:
 // a quarter of the bytes from L2 per triple of the one-j unit
 // (complete_unit), and no partial sums to add.
-__global__ __launch_bounds__(256, 2) void mfma3_complete_kernel(Triple3Args a, UnitGrid ug,
+__global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, UnitGrid ug,
                                                                 const int64_t* __restrict__ offs,
                                                                 int64_t unit_base,
                                                                 int64_t count) {
