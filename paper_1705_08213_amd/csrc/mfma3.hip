@@ -676,21 +676,29 @@ constexpr int64_t kJRun = 4;
 // otherwise).  A workgroup takes a run of kJRun consecutive middle vectors j
 // of one tile pair (I tile, K tile), one per wave, and each wave computes the
 // whole 64 x 64 (i, k) tile of S_xyz = G[i][k] + sum rho_i(1) D_j rho_k(1)
-// for its j over every field (4 x 4 blocks of one fp4 plane).  The unit's 4 i
-// blocks, 4 k blocks and its j rows (16 copies of one row each) travel
-// through the workgroup's LDS stage once per super-step for all four waves:
-// a quarter of the bytes from L2 per triple of the one-j unit
-// (complete_unit), and no partial sums to add.
+// for its j over every field (4 x 4 blocks of one fp4 plane).
+//
+// The four waves need the same rho(1) operands of the unit's 4 i blocks and
+// 4 k blocks; only D_j (and so the modulation of the k operands) is their
+// own.  So per super-step the rows travel through the workgroup's LDS stage
+// once (`raw`: 4 i blocks, 4 k blocks, and one block holding the run's j
+// rows, lane l the row j0 + min(l & 15, jn - 1)), each wave turns two of the
+// 8 row blocks into rho(1) nibbles and writes them to `planes`, and every
+// wave reads all 8 back.  The steps are skewed by one: in step s a wave
+// builds the planes of step s + 1 (and keeps its j word of step s + 1)
+// while it multiplies those of step s, so one barrier per step covers both
+// buffers: raw(s + 1) has landed, planes(s) are written, and the buffers of
+// step s - 1 are free (raw(s + 2) goes into the buffer of raw(s), which was
+// read in step s - 1).  The last, padded step takes plain loads.
 __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, UnitGrid ug,
                                                                 const int64_t* __restrict__ offs,
                                                                 int64_t unit_base,
                                                                 int64_t count) {
 #pragma clang fp contract(off)
   if (*a.complete == 0) return;  // uniform
-  constexpr int NB = 8 + kJRun, BPW = NB / 4;  // row blocks per step, per wave
-  static_assert(NB % 4 == 0, "every wave copies the same number of blocks");
-  __shared__ u4 stage[2][NB][64];  // 24 KB
-  __shared__ u4 outs[4][384];      // 24 KB: each wave's store staging
+  constexpr int NB = 9, BPW = 3;  // raw row blocks per step; copies per wave (the last idle)
+  __shared__ u4 raw[2][NB][64];        // 18 KB
+  __shared__ u4 planes[2][8][2][64];   // 32 KB: [step & 1][block][half][lane]; then store staging
   const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
   const int64_t n = a.n;
@@ -703,21 +711,21 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
   const bool active = wave < jn;
   const int64_t i0 = it * BI, k0 = kt * BK;
 
-  // Copies: blocks 0-3 rows i, 4-7 rows k, 8 + w the run's w-th j (16 copies
-  // of the row); a wave-uniform base (the block's first row, clamped) plus
-  // a 32-bit lane offset (r - rf < 16 rows of at most 2^28 bytes).
+  // Copies: blocks 0-3 rows i, 4-7 rows k, 8 the run's j rows; a
+  // wave-uniform base (the block's first row, clamped) plus a 32-bit lane
+  // offset (r - rf < 16 rows of at most 2^28 bytes).
   gbytes base[BPW];
   uint32_t off[BPW];
 #pragma unroll
   for (int t = 0; t < BPW; ++t) {
-    const int b = BPW * wave + t;
+    const int b = BPW * wave + t < NB ? BPW * wave + t : NB - 1;
     int64_t r0, r1;
     if (b < 8) {
       r0 = (b < 4 ? i0 + 16 * b : k0 + 16 * (b - 4));
       r1 = r0 + rl;
     } else {
-      r0 = j0 + (b - 8 < jn ? b - 8 : jn - 1);
-      r1 = r0;
+      r0 = j0;
+      r1 = j0 + (rl < jn ? rl : jn - 1);
     }
     const int64_t rf = r0 < n ? r0 : n - 1, r = r1 < n ? r1 : n - 1;
     const uint64_t bp = (uint64_t)(a.v + rf * a.ld);
@@ -728,8 +736,23 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
   auto issue = [&](int64_t st, int buf) {
 #pragma unroll
     for (int t = 0; t < BPW; ++t)
-      tile2::stage_row((const uint8_t*)(base[t] + st * 64 + off[t]),
-                       &stage[buf][BPW * wave + t][0]);
+      if (BPW * wave + t < NB)
+        tile2::stage_row((const uint8_t*)(base[t] + st * 64 + off[t]),
+                         &raw[buf][BPW * wave + t][0]);
+  };
+  // this wave's share of the planes: blocks 2 wave and 2 wave + 1, both halves
+  auto build = [&](int rbuf, int pbuf) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int b = 2 * wave + t;
+      const u4 x = raw[rbuf][b][lane];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const v8i r = tile2::rho1_nibbles_complete(word_of(x, 2 * h), word_of(x, 2 * h + 1));
+        planes[pbuf][b][h][lane] = u4{(unsigned)r[0], (unsigned)r[1], (unsigned)r[2],
+                                      (unsigned)r[3]};
+      }
+    }
   };
 
   v4f acc[4][4];
@@ -737,59 +760,58 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[m][c] = v4f{0, 0, 0, 0};
-  // one super-step; `complete`: no padding code in the step's words
-  auto body = [&](const u4 (&xa)[4], const u4 (&xk)[4], const u4& xj, auto complete) {
-    auto rho1_pair = [&](unsigned w0, unsigned w1) {
-      if constexpr (complete.value)
-        return tile2::rho1_nibbles_complete(w0, w1);
-      else
-        return tile2::nibbles32(tile2::rho1_16_f4<false>(w0), tile2::rho1_16_f4<false>(w1));
-    };
+  // the MFMAs of one half super-step from the 8 blocks' nibbles and j's word
+  auto multiply = [&](const v8i (&A)[4], const v8i (&K)[4], unsigned wj0, unsigned wj1) {
+    unsigned y[4], sg[4];
+    j_masks_f4(wj0, y, sg, nullptr);
+    j_masks_f4(wj1, y + 2, sg + 2, nullptr);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      unsigned y[4], sg[4];
-      j_masks_f4(word_of(xj, 2 * h), y, sg, nullptr);
-      j_masks_f4(word_of(xj, 2 * h + 1), y + 2, sg + 2, nullptr);
-      v8i A[4];
+    for (int c = 0; c < 4; ++c) {
+      v8i B;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) A[m] = rho1_pair(word_of(xa[m], 2 * h), word_of(xa[m], 2 * h + 1));
+      for (int q = 0; q < 4; ++q) B[q] = (int)mod_d((unsigned)K[c][q], y[q], sg[q]);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const v8i R = rho1_pair(word_of(xk[c], 2 * h), word_of(xk[c], 2 * h + 1));
-        v8i B;
+      for (int q = 4; q < 8; ++q) B[q] = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) B[q] = (int)mod_d((unsigned)R[q], y[q], sg[q]);
-#pragma unroll
-        for (int q = 4; q < 8; ++q) B[q] = 0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m][c] = tile2::mfma_f4(A[m], B, acc[m][c]);
-      }
+      for (int m = 0; m < 4; ++m) acc[m][c] = tile2::mfma_f4(A[m], B, acc[m][c]);
     }
   };
+  auto as_v8 = [](const u4& x) { return v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0}; };
 
-  // Whole super-steps through the stage: one barrier per step (every block
-  // has landed; the buffer read one step earlier is free), the words read
-  // before the next copy is issued.  Then the padded last step from plain
-  // loads.
   const int64_t nfull = a.n_f / 256;
-  if (nfull > 0) issue(0, 0);
+  u4 xj = u4{0, 0, 0, 0};  // this wave's j word of the step to multiply next
+  if (nfull > 0) {
+    issue(0, 0);
+    if (nfull > 1) issue(1, 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    build(0, 0);
+    xj = raw[0][8][16 * g + wave];
+  }
   for (int64_t st = 0; st < nfull; ++st) {
     const int buf = (int)(st & 1);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's blocks have landed
-    __syncthreads();                                   // every wave's have; buf ^ 1 is free
-    u4 xa[4], xk[4], xj;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // raw(st + 1) of this wave has landed
+    __syncthreads();  // every wave's has; planes(st) are written; step st - 1's buffers are free
+    const u4 xj_now = xj;
+    if (st + 1 < nfull) {
+      xj = raw[buf ^ 1][8][16 * g + wave];
+      if (st + 2 < nfull) issue(st + 2, buf);
+      build(buf ^ 1, buf ^ 1);
+    }
     if (active) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) xa[m] = stage[buf][m][lane];
+      for (int h = 0; h < 2; ++h) {
+        v8i A[4], K[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) xk[c] = stage[buf][4 + c][lane];
-      xj = stage[buf][8 + wave][lane];
+        for (int m = 0; m < 4; ++m) {
+          A[m] = as_v8(planes[buf][m][h][lane]);
+          K[m] = as_v8(planes[buf][4 + m][h][lane]);
+        }
+        multiply(A, K, word_of(xj_now, 2 * h), word_of(xj_now, 2 * h + 1));
+      }
     }
-    if (st + 1 < nfull) issue(st + 1, buf ^ 1);
-    if (active) body(xa, xk, xj, std::true_type{});
   }
-  if (!active) return;
-  if (nfull * 256 < a.n_f) {
+  if (nfull * 256 < a.n_f && active) {
     const int64_t kb = nfull * 64 + 16 * g;
     u4 xa[4], xk[4];
 #pragma unroll
@@ -799,10 +821,25 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
       r = k0 + 16 * m + rl;
       xk[m] = load_fields64(a.v + (r < n ? r : n - 1) * a.ld, kb, a.n_f);
     }
-    body(xa, xk, load_fields64(a.v + j * a.ld, kb, a.n_f), std::false_type{});
+    const u4 xt = load_fields64(a.v + j * a.ld, kb, a.n_f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      v8i A[4], K[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        A[m] = tile2::nibbles32(tile2::rho1_16_f4<false>(word_of(xa[m], 2 * h)),
+                                tile2::rho1_16_f4<false>(word_of(xa[m], 2 * h + 1)));
+        K[m] = tile2::nibbles32(tile2::rho1_16_f4<false>(word_of(xk[m], 2 * h)),
+                                tile2::rho1_16_f4<false>(word_of(xk[m], 2 * h + 1)));
+      }
+      multiply(A, K, word_of(xt, 2 * h), word_of(xt, 2 * h + 1));
+    }
   }
+  __syncthreads();  // every wave is done with `planes`: it now stages the stores
+  if (!active) return;
 
   // Epilogue: 4 block rows of 16 triples per lane for this wave's j.
+  u4* outs = &planes[0][0][0][0] + 384 * wave;
   tile2::static_for<4>([&](auto mc) {
     constexpr int m = decltype(mc)::value;
     v4i xyz[4];
@@ -812,7 +849,7 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
       xyz[c] = v4i{tile2::f4_count(x[0]), tile2::f4_count(x[1]), tile2::f4_count(x[2]),
                    tile2::f4_count(x[3])};
     }
-    complete_block_row<true>(a, j, i0 + 16 * m, k0, xyz, outs[wave]);
+    complete_block_row<true>(a, j, i0 + 16 * m, k0, xyz, outs);
   });
 }
 
