@@ -283,14 +283,18 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   const int64_t row_end = i_end < n_v - 2 ? i_end : n_v - 2;  // first index below n_v - 2
   if (row_end <= i_begin && !counts && !zero) return CCC_OK;  // nothing to compute or write
   // workspace: offsets of the tetrahedral work units (per tile pair; the
-  // one-j grid, then the grid of the complete-data kernel's runs of j),
-  // then (if needed) counts, then (MFMA path) the complete-data flag and the
-  // rho(1) Gram matrix of rows [g0, n_v) used by complete-data units; g0 is
-  // i_begin rounded down to the unit tile
+  // one-j grid, the grid of the complete-data kernel's runs of j, the fp4
+  // general kernel's grid of 32-row tiles), then (if needed) counts, then
+  // (MFMA path) the complete-data flag and the rho(1) Gram matrix of rows
+  // [g0, n_v) used by complete-data units; g0 is i_begin rounded down to the
+  // unit tile
   const ccc::UnitGrid ug = ccc::unit_grid(n_v, ccc::kUnitTile, i_begin, row_end);
   const size_t offs_bytes = ((size_t)(ccc::grid_pairs(ug) + 1) * 8 + 255) / 256 * 256;
+  const ccc::UnitGrid ug32 = ccc::unit_grid(n_v, ccc::kRunTile, i_begin, row_end);
+  const size_t gen_bytes = ((size_t)(ccc::grid_pairs(ug32) + 1) * 8 + 255) / 256 * 256;
   const size_t cnt_bytes = counts ? 0 : ((size_t)n_v * 16 + 255) / 256 * 256;
-  const size_t head_bytes = 2 * offs_bytes + cnt_bytes + 256;  // offsets, counts, flag
+  // offsets (one-j grid, runs grid, 32-row runs grid), counts, flag
+  const size_t head_bytes = 2 * offs_bytes + gen_bytes + cnt_bytes + 256;
   const int64_t g0 = i_begin / ccc::kUnitTile * ccc::kUnitTile, ng = n_v - g0;
   bool use_gram = o.path != CCC_PATH_POPCOUNT && ng <= kGramMaxRows && i_begin < row_end;
   if (fixed) {
@@ -302,7 +306,7 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   if ((st = fixed ? noalloc_scratch(&ws) : ccc::workspace(head_bytes + gram_bytes, &ws)))
     return st;
   char* wsb = static_cast<char*>(ws);
-  int32_t* cnt = counts ? counts : reinterpret_cast<int32_t*>(wsb + 2 * offs_bytes);
+  int32_t* cnt = counts ? counts : reinterpret_cast<int32_t*>(wsb + 2 * offs_bytes + gen_bytes);
   if (n_v < 3)
     return ccc::launch_count1_zero(v, ld, n_v, n_f, cnt, 0, zero, stream) == hipSuccess
                ? CCC_OK
@@ -327,8 +331,10 @@ int three_way(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int64_t i_
   a.g0 = g0;
   a.ng = use_gram ? ng : 0;
   // the complete-data kernel (fp4 operands, with the Gram matrix)
-  a.complete = use_gram && f4 ? reinterpret_cast<int*>(wsb + 2 * offs_bytes + cnt_bytes) : nullptr;
+  a.complete = use_gram && f4 ? reinterpret_cast<int*>(wsb + 2 * offs_bytes + gen_bytes + cnt_bytes)
+                              : nullptr;
   a.offs_run = reinterpret_cast<int64_t*>(wsb + offs_bytes);
+  a.offs_gen = reinterpret_cast<int64_t*>(wsb + 2 * offs_bytes);
   hipError_t e = o.path == CCC_PATH_POPCOUNT ? ccc::launch_pop3(a, stream)
                                              : ccc::launch_mfma3(a, stream);
   return e == hipSuccess ? CCC_OK : CCC_ERR_HIP;

@@ -54,8 +54,10 @@ struct Pair2Args {
 // sums of quarter-multiples, at most n_f, stay exact); int8 beyond.
 constexpr int64_t kF4MaxFields = int64_t(1) << 22;
 
-// Row tile of the 3-way work units (both 3-way kernels use it).
+// Row tile of the 3-way work units (one-j units and the complete-data
+// kernel's runs), and of the fp4 general kernel's runs of middle vectors.
 constexpr int64_t kUnitTile = 64;
+constexpr int64_t kRunTile = 32;
 
 // Tetrahedral work units of the 3-way kernels.  Rows are cut into b-row
 // tiles; a unit is (I tile it, K tile kt, middle vectors j .. j + run - 1)
@@ -218,6 +220,9 @@ struct Triple3Args {
   // fields present.
   int* complete;
   int64_t* offs_run;
+  // Unit offsets of the fp4 general kernel's grid (32-row tiles, runs of
+  // four middle vectors).
+  int64_t* offs_gen;
 };
 
 enum Path { kPathPopcount = 1, kPathMfma = 2 };

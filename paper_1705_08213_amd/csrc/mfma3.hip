@@ -853,6 +853,213 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
   });
 }
 
+// General 3-way kernel on fp4 operands (calls that are not complete; it
+// exits at once when the complete-data flag is set).  A workgroup takes a
+// run of kJRun consecutive middle vectors j of one pair of 32-row tiles
+// (I tile, K tile), one per wave; each wave computes the eight MFMA planes
+// of the whole 32 x 32 (i, k) tile for its j over every field (2 x 2 blocks
+// x 8 planes of accumulators).  The rho(1) and P planes of the unit's 2 i
+// and 2 k blocks do not depend on j: per super-step the rows travel through
+// the workgroup's LDS stage once (`raw`: 2 i blocks, 2 k blocks, and one
+// block of the run's j rows, lane l the row j0 + min(l & 15, jn - 1)), wave
+// w turns row block w into its two planes and writes them to `planes`, and
+// every wave reads all four back; only j's masks and the modulation of the
+// k planes by D_j and P_j are each wave's own.  The steps are skewed by one
+// as in mfma3_complete_kernel, so one barrier per step covers both buffers.
+__global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGrid ug,
+                                                           const int64_t* __restrict__ offs,
+                                                           int64_t unit_base, int64_t count) {
+#pragma clang fp contract(off)
+  if (a.complete && *a.complete) return;  // uniform: mfma3_complete_kernel covers the call
+  constexpr int NB = 5, BPW = 2;  // raw row blocks per step; copies per wave (3 idle slots)
+  __shared__ u4 raw[2][NB][64];            // 10 KB
+  __shared__ u4 planes[2][4][2][2][64];    // 32 KB: [step & 1][block][half][rho(1), P][lane]
+  const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
+  const int64_t n = a.n;
+  const int64_t u = unit_base + xcd_unit(blockIdx.x, count);
+  int64_t j0, it, kt, jlo, jhi;
+  unit_coords(u, ug, offs, j0, it, kt);
+  pair_j_range(ug, it, kt, jlo, jhi);
+  const int64_t jn = jhi - j0 < kJRun ? jhi - j0 : kJRun;  // middle vectors of this run
+  const int64_t j = j0 + (wave < jn ? wave : jn - 1);      // inactive waves repeat the last
+  const bool active = wave < jn;
+  const int64_t i0 = it * kRunTile, k0 = kt * kRunTile;
+
+  // Copies: blocks 0-1 rows i, 2-3 rows k, 4 the run's j rows; a
+  // wave-uniform base (the block's first row, clamped) plus a 32-bit lane
+  // offset (r - rf < 16 rows of at most 2^28 bytes).
+  gbytes base[BPW];
+  uint32_t off[BPW];
+#pragma unroll
+  for (int t = 0; t < BPW; ++t) {
+    const int b = BPW * wave + t < NB ? BPW * wave + t : NB - 1;
+    int64_t r0, r1;
+    if (b < 4) {
+      r0 = (b < 2 ? i0 + 16 * b : k0 + 16 * (b - 2));
+      r1 = r0 + rl;
+    } else {
+      r0 = j0;
+      r1 = j0 + (rl < jn ? rl : jn - 1);
+    }
+    const int64_t rf = r0 < n ? r0 : n - 1, r = r1 < n ? r1 : n - 1;
+    const uint64_t bp = (uint64_t)(a.v + rf * a.ld);
+    base[t] = (gbytes)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
+    off[t] = (uint32_t)((r - rf) * a.ld + 16 * g);
+  }
+  auto issue = [&](int64_t st, int buf) {
+#pragma unroll
+    for (int t = 0; t < BPW; ++t)
+      if (BPW * wave + t < NB)
+        tile2::stage_row((const uint8_t*)(base[t] + st * 64 + off[t]),
+                         &raw[buf][BPW * wave + t][0]);
+  };
+  // the planes of one row block's 16 bytes: per half, rho(1) and P
+  auto planes_of = [](const u4& x, int h, u4& R, u4& P) {
+    unsigned r0[2], p0[2], r1[2], p1[2];
+    tile2::planes32_f4(word_of(x, 2 * h), word_of(x, 2 * h + 1), r0, p0, r1, p1);
+    R = u4{r0[0], r0[1], r1[0], r1[1]};
+    P = u4{p0[0], p0[1], p1[0], p1[1]};
+  };
+  // this wave's share: row block `wave` (0-1 rows i, 2-3 rows k), both halves
+  auto build = [&](int rbuf, int pbuf) {
+    const u4 x = raw[rbuf][wave][lane];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      u4 R, P;
+      planes_of(x, h, R, P);
+      planes[pbuf][wave][h][0][lane] = R;
+      planes[pbuf][wave][h][1][lane] = P;
+    }
+  };
+
+  v4f acc[2][2][8];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[m][c][e] = v4f{0, 0, 0, 0};
+  auto as_v8 = [](const u4& x) { return v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0}; };
+  // the MFMAs of one half super-step: planes of rows i (AR, AP) and k (KR,
+  // KP), j's two words
+  auto multiply = [&](const u4 (&AR)[2], const u4 (&AP)[2], const u4 (&KR)[2], const u4 (&KP)[2],
+                      unsigned wj0, unsigned wj1) {
+    unsigned y[4], sg[4], pm[4];
+    j_masks32_f4(wj0, wj1, y, sg, pm);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      v8i B[4];  // y z = D R, D P, P R, P P
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const unsigned R = word_of(KR[c], q), P = word_of(KP[c], q);
+        B[0][q] = (int)mod_d(R, y[q], sg[q]);
+        B[1][q] = (int)mod_d(P, y[q], sg[q]);
+        B[2][q] = (int)(R & pm[q]);
+        B[3][q] = (int)(P & pm[q]);
+      }
+#pragma unroll
+      for (int yz = 0; yz < 4; ++yz)
+#pragma unroll
+        for (int q = 4; q < 8; ++q) B[yz][q] = 0;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const v8i ar = as_v8(AR[m]), ap = as_v8(AP[m]);
+#pragma unroll
+        for (int yz = 0; yz < 4; ++yz) {
+          acc[m][c][yz] = tile2::mfma_f4(ar, B[yz], acc[m][c][yz]);
+          acc[m][c][4 + yz] = tile2::mfma_f4(ap, B[yz], acc[m][c][4 + yz]);
+        }
+      }
+    }
+  };
+
+  const int64_t nfull = a.n_f / 256;
+  u4 xj = u4{0, 0, 0, 0};  // this wave's j word of the step to multiply next
+  if (nfull > 0) {
+    issue(0, 0);
+    if (nfull > 1) issue(1, 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    build(0, 0);
+    xj = raw[0][4][16 * g + wave];
+  }
+  for (int64_t st = 0; st < nfull; ++st) {
+    const int buf = (int)(st & 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // raw(st + 1) of this wave has landed
+    __syncthreads();  // every wave's has; planes(st) are written; step st - 1's buffers are free
+    const u4 xj_now = xj;
+    if (st + 1 < nfull) {
+      xj = raw[buf ^ 1][4][16 * g + wave];
+      if (st + 2 < nfull) issue(st + 2, buf);
+      build(buf ^ 1, buf ^ 1);
+    }
+    if (active) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        u4 AR[2], AP[2], KR[2], KP[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          AR[m] = planes[buf][m][h][0][lane];
+          AP[m] = planes[buf][m][h][1][lane];
+          KR[m] = planes[buf][2 + m][h][0][lane];
+          KP[m] = planes[buf][2 + m][h][1][lane];
+        }
+        multiply(AR, AP, KR, KP, word_of(xj_now, 2 * h), word_of(xj_now, 2 * h + 1));
+      }
+    }
+  }
+  if (nfull * 256 < a.n_f && active) {  // the padded last step: plain loads, all four blocks
+    const int64_t kb = nfull * 64 + 16 * g;
+    u4 xr[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int64_t r = (b < 2 ? i0 + 16 * b : k0 + 16 * (b - 2)) + rl;
+      xr[b] = load_fields64(a.v + (r < n ? r : n - 1) * a.ld, kb, a.n_f);
+    }
+    const u4 xt = load_fields64(a.v + j * a.ld, kb, a.n_f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      u4 AR[2], AP[2], KR[2], KP[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        planes_of(xr[m], h, AR[m], AP[m]);
+        planes_of(xr[2 + m], h, KR[m], KP[m]);
+      }
+      multiply(AR, AP, KR, KP, word_of(xt, 2 * h), word_of(xt, 2 * h + 1));
+    }
+  }
+  __syncthreads();  // every wave is done with `planes`: it now stages the stores
+  if (!active) return;
+
+  // Epilogue: entry 4a + 2b + c; lane holds rows i0 + 16m + 4g + e of column
+  // k0 + 16c + rl.
+  u4* outs = &planes[0][0][0][0][0] + 384 * wave;
+  double wj[2], wk[2][2];
+  triple_factors(a, j, wj);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) triple_factors(a, k0 + 16 * c + rl, wk[c]);
+  tile2::static_for<2>([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + 16 * m + 4 * g + e;
+      double wi[2];
+      triple_factors(a, i, wi);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int64_t k = k0 + 16 * c + rl;
+        int S[8], t[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) S[x] = tile2::f4_count(acc[m][c][x][e]);
+        table3_f4(S, t);
+        emit_triple_staged(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c], outs);
+      }
+    }
+  });
+}
+
 // *flag = 1 if every row of [r0, n) has all n_f fields present (one
 // workgroup; its threads read the counts with a stride).
 __global__ __launch_bounds__(1024) void complete3_flag_kernel(const int32_t* __restrict__ counts,
@@ -964,7 +1171,7 @@ hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream) {
       e = launch_units(mfma3_complete_kernel, a, BI, nullptr, stream, kJRun, a.offs_run);
   }
   if (e == hipSuccess)
-    e = a.f4 ? launch_units(mfma3_kernel<true>, a, BI, nullptr, stream)
+    e = a.f4 ? launch_units(mfma3_run_kernel, a, kRunTile, nullptr, stream, kJRun, a.offs_gen)
              : launch_units(mfma3_kernel<false>, a, BI, nullptr, stream);
   timing_end(stream);
   return e;

@@ -1,7 +1,7 @@
 // Host-side check of the 3-way work-unit enumeration (UnitGrid helpers of
-// the library's kernels.h, compiled for the host): for each case and run
-// length (1 middle vector per unit, and the complete-data kernel's runs of
-// 4), the units cover every triple i < j < k with i in
+// the library's kernels.h, compiled for the host): for each case, tile (64,
+// 32, 16 rows) and run length (1 middle vector per unit, and the runs of 4
+// of the complete-data and fp4 general kernels), the units cover every triple i < j < k with i in
 // [i_begin, min(i_end, n-2)) exactly once, every unit lies inside its tile
 // pair, and the XCD remap of a grid is a permutation.  Also the 2-way strip order of squares (strip_square) is a
 // one-to-one map onto each row range's squares.  Prints "ok <cases>" and
@@ -91,13 +91,13 @@ int main() {
   int count = 0;
   for (int64_t run : {1, 4})
     for (const auto& c : cases) {
-      if (check(c[0], c[1], c[2], 64, run)) return 1;
-      ++count;
+      if (check(c[0], c[1], c[2], 64, run) || check(c[0], c[1], c[2], 32, run)) return 1;
+      count += 2;
     }
   srand(7);
   for (int r = 0; r < 40; ++r) {
     const long n = 3 + rand() % 180, ib = rand() % (n + 1), ie = ib + rand() % (n + 1 - ib);
-    const long b = (r & 1) ? 64 : 16;
+    const long b = (r % 3 == 0) ? 64 : (r % 3 == 1 ? 32 : 16);
     if (check(n, ib, ie, b, (r & 2) ? 4 : 1)) return 1;
     ++count;
   }
