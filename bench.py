@@ -322,8 +322,8 @@ def bench_3way(args, lib, missing, workload):
                 frac=ach / peak, traffic=None,
                 traffic_unit="bytes per launch (FETCH_SIZE+WRITE_SIZE, scaled)",
                 algorithmic_bytes=alg_bytes,
-                kernel="mfma3_complete_kernel" if missing == 0.0 and fmt == "fp4"
-                else "mfma3_kernel", kernel_ms=kms,
+                kernel=("mfma3_complete_kernel" if missing == 0.0 else "mfma3_run_kernel")
+                if fmt == "fp4" else "mfma3_kernel", kernel_ms=kms,
                 operands=fmt, ops_per_comparison=int(ops_per))
     if fmt == "fp4":
         roof["traffic"] = committed_traffic(

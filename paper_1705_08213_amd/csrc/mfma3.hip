@@ -1,24 +1,35 @@
-// mfma3.hip -- 3-way tallies on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
+// mfma3.hip -- 3-way tallies on the matrix cores (fp4 or int8 operands).
 //
 // For a fixed middle vector j (Sec. 2.2, Eq. (5)):
 //   C_ijk(a,b,c) = sum_q rho_i(a) * (rho_j(b) rho_k(c))
-// i.e. a 2-way product of the i-side planes R_a against j-modulated k-side
-// planes M_bc[k][q] = rho_{j,q}(b) rho_{k,q}(c) in {0,1,2,4}.  This plays the
-// role of the paper's X_{j,xi} construction (Table 1), which restricts a 2-way
-// tally by the genotype of v_j; here the restriction is folded into the
-// operand values, so one pass over the fields gives all 8 entries
-// (8 int8 MACs per comparison).
+// i.e. a 2-way product of i-side planes against j-modulated k-side planes.
+// This plays the role of the paper's X_{j,xi} construction (Table 1), which
+// restricts a 2-way tally by the genotype of v_j; here the restriction is
+// folded into the operand values, so one pass over the fields gives all 8
+// entries (8 MACs per comparison).
 //
-// Building M_bc costs one v_perm_b32 per 4 bytes: the selector is
-// code_k | J_b(code_j), with J_b = 0 where rho_j(b) = 1 (pick rho_k(c) from
-// the low table), 4 where rho_j(b) = 2 (pick 2 rho_k(c) from the high
-// table) and 8 where rho_j(b) = 0 (selectors 8..11 replicate the sign bit of
-// a table byte, and every table byte is below 0x80, so they give 0).
+// Kernels:
+//   mfma3_run_kernel       fp4, every call that is not complete: units of four
+//                          consecutive j over a pair of 32-row tiles, one j per
+//                          wave, the i and k planes shared through LDS;
+//   mfma3_complete_kernel  fp4, calls whose every row is complete (a device
+//                          flag picks it): one plane, units of four j over a
+//                          pair of 64-row tiles;
+//   mfma3_kernel           int8 operands: units of one j over a pair of 64-row
+//                          tiles, 2 x 2 waves; a unit whose rows are complete
+//                          takes the one-plane form together;
+//   gram1_kernel           the rho(1) Gram matrix of the complete-data formula.
 //
-// Schedule: a work unit is (I tile, K tile, j) with I tile rows below j and K
-// tile columns above j (tetrahedral: only i < j < k is ever stored).  A
-// workgroup is 2 x 2 waves over a (32 WI) x (32 WK) tile for one j; waves
-// whose whole tile has no valid (i, k) exit at once.
+// int8 operands: M_bc[k][q] = rho_{j,q}(b) rho_{k,q}(c) in {0,1,2,4}, one
+// v_perm_b32 per 4 bytes: the selector is code_k | J_b(code_j), with J_b = 0
+// where rho_j(b) = 1 (pick rho_k(c) from the low table), 4 where rho_j(b) = 2
+// (pick 2 rho_k(c) from the high table) and 8 where rho_j(b) = 0 (selectors
+// 8..11 replicate the sign bit of a table byte, and every table byte is below
+// 0x80, so they give 0).
+//
+// Schedule: a work unit is (I tile, K tile, j or a run of j) with I tile rows
+// below j and K tile columns above j (tetrahedral: only i < j < k is ever
+// stored).
 //
 // Complete data (every row of a unit, and v_j, has all n_f fields present, as
 // the 1-way counts of the call say): with rho(0) = 2 - rho(1) on every field
@@ -29,8 +40,7 @@
 //   C(1,1,1) = S_xyz,  C(1,1,0) = 2 S_xy - S_xyz, ...,
 //   C(0,0,0) = 8 n_f - 4 (n_i + n_j + n_k) + 2 (S_xy + S_xz + S_yz) - S_xyz
 // (expand the product of (2 - x) and x factors).  One MFMA plane replaces
-// eight.  Such a unit is computed by all four waves on one 64 x 64 tile, each
-// over a quarter of the fields, and the partial sums are added through LDS.
+// eight.
 #include <type_traits>
 
 #include "tile2.h"
@@ -159,161 +169,12 @@ __device__ __forceinline__ void table3_f4(const int (&S)[8], int (&t)[8]) {
   }
 }
 
-// fp4 body of general_wave (see there).
-__device__ __forceinline__ void general_wave_f4(const Triple3Args& a, int64_t j, int64_t row0,
-                                                int64_t col0, bool active,
-                                                const uint8_t* const (&pa)[WI],
-                                                const uint8_t* const (&pk)[WK],
-                                                const uint8_t* pj, u4* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, rl = lane & 15;
-  const int64_t n = a.n;
-  v4f acc[WI][WK][8];
-#pragma unroll
-  for (int m = 0; m < WI; ++m)
-#pragma unroll
-    for (int c = 0; c < WK; ++c)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) acc[m][c][e] = v4f{0, 0, 0, 0};
-
-  auto body = [&](const u4 (&xa)[WI], const u4 (&xk)[WK], const u4& xj) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      unsigned y[4], sg[4], pm[4];
-      j_masks32_f4(word_of(xj, 2 * h), word_of(xj, 2 * h + 1), y, sg, pm);
-      v8i AR[WI], AP[WI];
-#pragma unroll
-      for (int m = 0; m < WI; ++m) {
-        unsigned r0[2], p0[2], r1[2], p1[2];
-        tile2::planes32_f4(word_of(xa[m], 2 * h), word_of(xa[m], 2 * h + 1), r0, p0, r1, p1);
-        AR[m] = tile2::operand_f4(r0, r1);
-        AP[m] = tile2::operand_f4(p0, p1);
-      }
-#pragma unroll
-      for (int c = 0; c < WK; ++c) {
-        unsigned r0[2], p0[2], r1[2], p1[2];
-        tile2::planes32_f4(word_of(xk[c], 2 * h), word_of(xk[c], 2 * h + 1), r0, p0, r1, p1);
-        const unsigned R[4] = {r0[0], r0[1], r1[0], r1[1]};
-        const unsigned P[4] = {p0[0], p0[1], p1[0], p1[1]};
-        v8i B[4];  // y z = D R, D P, P R, P P
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          B[0][q] = (int)mod_d(R[q], y[q], sg[q]);
-          B[1][q] = (int)mod_d(P[q], y[q], sg[q]);
-          B[2][q] = (int)(R[q] & pm[q]);
-          B[3][q] = (int)(P[q] & pm[q]);
-        }
-#pragma unroll
-        for (int yz = 0; yz < 4; ++yz)
-#pragma unroll
-          for (int q = 4; q < 8; ++q) B[yz][q] = 0;
-#pragma unroll
-        for (int m = 0; m < WI; ++m)
-#pragma unroll
-          for (int yz = 0; yz < 4; ++yz) {
-            acc[m][c][yz] = tile2::mfma_f4(AR[m], B[yz], acc[m][c][yz]);
-            acc[m][c][4 + yz] = tile2::mfma_f4(AP[m], B[yz], acc[m][c][4 + yz]);
-          }
-      }
-    }
-  };
-
-  // Whole super-steps through the workgroup's LDS stage: the unit's 2 WI
-  // i blocks, 2 WK k blocks and the j row (16 rows x 64 bytes per block, the
-  // j block 16 copies of one row), three blocks copied per wave, one barrier
-  // per step (every block has landed; the buffer read one step earlier is
-  // free).  Inactive waves only copy.  Then the masked tail from plain loads.
-  constexpr int NB = 2 * WI + 2 * WK + 1, BPW = (NB + 3) / 4;
-  auto stage = reinterpret_cast<u4(*)[NB][64]>(lds);
-  const int64_t I0 = row0 - (wave & 1) * 16 * WI, K0 = col0 - (wave >> 1) * 16 * WK;
-  // each copy: a wave-uniform base (the block's first row, clamped; read
-  // from lane 0 so the compiler knows it is uniform) plus a fixed 32-bit
-  // lane offset (the j block: 16 copies of row j)
-  const int wu = __builtin_amdgcn_readfirstlane(wave);
-  const uint8_t* base[BPW];
-  uint32_t off[BPW];
-#pragma unroll
-  for (int t = 0; t < BPW; ++t) {
-    const int b = BPW * wu + t;
-    const int64_t r0 = b < 2 * WI ? I0 + 16 * b : (b < NB - 1 ? K0 + 16 * (b - 2 * WI) : j);
-    const int64_t r1 = b < NB - 1 ? r0 + rl : j;
-    const int64_t rf = r0 < n ? r0 : n - 1, r = r1 < n ? r1 : n - 1;
-    const uint64_t bp = (uint64_t)(a.v + rf * a.ld);
-    base[t] = (const uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32))
-                                << 32) |
-                               (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
-    off[t] = (uint32_t)((r - rf) * a.ld + 16 * g);
-  }
-  const int64_t nfull = a.n_f / 256;
-  auto issue = [&](int64_t st, int buf) {
-#pragma unroll
-    for (int t = 0; t < BPW; ++t)
-      if (BPW * wu + t < NB)
-        tile2::stage_row(base[t] + st * 64 + off[t], &stage[buf][BPW * wu + t][0]);
-  };
-  const int ia = (wave & 1) * WI, kb = 2 * WI + (wave >> 1) * WK;
-  if (nfull > 0) issue(0, 0);
-  for (int64_t st = 0; st < nfull; ++st) {
-    const int buf = (int)(st & 1);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's blocks have landed
-    __syncthreads();                                   // every wave's have; buf ^ 1 is free
-    u4 xa[WI], xk[WK], xj;  // read before the next copy is issued
-    if (active) {
-#pragma unroll
-      for (int c = 0; c < WK; ++c) xk[c] = stage[buf][kb + c][lane];
-#pragma unroll
-      for (int m = 0; m < WI; ++m) xa[m] = stage[buf][ia + m][lane];
-      xj = stage[buf][NB - 1][lane];
-    }
-    if (st + 1 < nfull) issue(st + 1, buf ^ 1);
-    if (active) body(xa, xk, xj);
-  }
-  if (!active) return;
-  if (nfull * 256 < a.n_f) {
-    const int64_t kb = nfull * 64 + 16 * g;
-    u4 xa[WI], xk[WK];
-#pragma unroll
-    for (int m = 0; m < WI; ++m) xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
-#pragma unroll
-    for (int c = 0; c < WK; ++c) xk[c] = load_fields64(pk[c] - 16 * g, kb, a.n_f);
-    body(xa, xk, load_fields64(pj - 16 * g, kb, a.n_f));
-  }
-
-  double wj[2], wk[WK][2];
-  triple_factors(a, j, wj);
-#pragma unroll
-  for (int c = 0; c < WK; ++c) triple_factors(a, col0 + 16 * c + rl, wk[c]);
-#pragma unroll
-  for (int m = 0; m < WI; ++m)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t i = row0 + 16 * m + 4 * g + e;
-      double wi[2];
-      triple_factors(a, i, wi);
-#pragma unroll
-      for (int c = 0; c < WK; ++c) {
-        const int64_t k = col0 + 16 * c + rl;
-        int S[8], t[8];
-#pragma unroll
-        for (int x = 0; x < 8; ++x) S[x] = tile2::f4_count(acc[m][c][x][e]);
-        table3_f4(S, t);
-        // stage the stores past the workgroup's stage buffers (other waves may
-        // still read those): 384 x 16 bytes per wave
-        emit_triple_staged(a, k > j && k < n && i < j, i, j, k, t, wi, wj, wk[c],
-                           lds + 2 * NB * 64 + 384 * wave);
-      }
-    }
-}
-
-// General unit, one wave: the (16 WI) x (16 WK) tile of (i, k) at rows row0..,
-// columns col0.. for middle vector j, eight MFMA planes.  `active`: the tile
-// holds a triple i < j < k.  int8 form: inactive waves return at once.  fp4
-// form: every wave of the workgroup calls it; the unit's rows of the next
-// super-step travel into the workgroup's LDS stage (`lds`) while the current
-// one is multiplied, and inactive waves only take part in the copies.
-template <bool F4>
+// General unit, one wave, int8 operands: the (16 WI) x (16 WK) tile of
+// (i, k) at rows row0.., columns col0.. for middle vector j, eight MFMA
+// planes.  `active`: the tile holds a triple i < j < k; inactive waves return
+// at once.
 __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, int64_t row0,
-                                             int64_t col0, bool active, u4* lds) {
+                                             int64_t col0, bool active) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
   const int64_t n = a.n;
@@ -332,10 +193,6 @@ __device__ __forceinline__ void general_wave(const Triple3Args& a, int64_t j, in
   }
   const uint8_t* pj = a.v + j * a.ld + 16 * g;
 
-  if constexpr (F4) {
-    general_wave_f4(a, j, row0, col0, active, pa, pk, pj, lds);
-    return;
-  }
   if (!active) return;
 
   v4i acc[WI][WK][8];
@@ -501,12 +358,10 @@ __device__ __forceinline__ void complete_block_row(const Triple3Args& a, int64_t
   }
 }
 
-// Complete-data unit (see the notes at the top): all four waves build the
-// same 64 x 64 tile of S_xyz over a quarter of the 256-field super-steps
-// each, the partial sums meet in LDS, and wave w finishes rows 16w..16w+15.
-// fp4 form: rho_j(1) = 1 + D_j on every field of complete data, so
-// S_xyz = G[i][k] + sum rho_i(1) D_j rho_k(1): one plane, modulated by D_j.
-template <bool F4>
+// Complete-data unit of the int8 form (see the notes at the top): all four
+// waves build the same 64 x 64 tile of S_xyz over a quarter of the 256-field
+// super-steps each, the partial sums meet in LDS, and wave w finishes rows
+// 16w..16w+15.
 __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, int64_t i0,
                                               int64_t k0, v4i (*part)[16][64]) {
 #pragma clang fp contract(off)
@@ -524,122 +379,53 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
   }
   const uint8_t* pj = a.v + j * a.ld + 16 * g;
 
-  using Acc = std::conditional_t<F4, v4f, v4i>;
-  Acc acc[4][4];
+  v4i acc[4][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[m][c] = Acc{0, 0, 0, 0};
-
-  // fp4 step; `complete`: no padding code in the step's words
-  auto body_f4 = [&](auto& acc4, const u4 (&xa)[4], const u4 (&xk)[4], const u4& xj,
-                     auto complete) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      unsigned y[4], sg[4];
-      j_masks_f4(word_of(xj, 2 * h), y, sg, nullptr);
-      j_masks_f4(word_of(xj, 2 * h + 1), y + 2, sg + 2, nullptr);
-      v8i A[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-        A[m] = tile2::nibbles32(tile2::rho1_16_f4<complete.value>(word_of(xa[m], 2 * h)),
-                                tile2::rho1_16_f4<complete.value>(word_of(xa[m], 2 * h + 1)));
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const unsigned z0 = tile2::rho1_16_f4<complete.value>(word_of(xk[c], 2 * h));
-        const unsigned z1 = tile2::rho1_16_f4<complete.value>(word_of(xk[c], 2 * h + 1));
-        const unsigned R[4] = {z0 & tile2::kNib2, (z0 >> 2) & tile2::kNib2, z1 & tile2::kNib2,
-                               (z1 >> 2) & tile2::kNib2};
-        v8i B;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) B[q] = (int)mod_d(R[q], y[q], sg[q]);
-#pragma unroll
-        for (int q = 4; q < 8; ++q) B[q] = 0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc4[m][c] = tile2::mfma_f4(A[m], B, acc4[m][c]);
-      }
-    }
-  };
+    for (int c = 0; c < 4; ++c) acc[m][c] = v4i{0, 0, 0, 0};
 
   const int64_t steps = (a.n_f + 255) / 256;
   const int64_t s_begin = steps * wave / 4, s_end = steps * (wave + 1) / 4;
-  if constexpr (F4) {
-    // Whole steps alternate between two register sets, the next step's words
-    // loading while the current one computes; then the padded last step, if
-    // it falls in this wave's range.
-    const int64_t n_whole = a.n_f / 256;
-    const int64_t e_whole = s_end < n_whole ? s_end : n_whole;
-    auto load = [&](int64_t st, u4 (&xa)[4], u4 (&xk)[4], u4& xj) {
-      const int64_t kb = st * 64;
+  for (int64_t st = s_begin; st < s_end; ++st) {
+    const int64_t kb = st * 64;
+    const bool full = (kb + 64) * 4 <= a.n_f;
+    u4 xa[4], xk[4], xj;
+    if (full) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         xa[m] = *reinterpret_cast<const u4*>(pa[m] + kb);
         xk[m] = *reinterpret_cast<const u4*>(pk[m] + kb);
       }
       xj = *reinterpret_cast<const u4*>(pj + kb);
-    };
-    u4 ea[4], ek[4], ej, oa[4], ok[4], oj;
-    int64_t st = s_begin;
-    if (st < e_whole) load(st, ea, ek, ej);
-    for (; st + 1 < e_whole; st += 2) {
-      load(st + 1, oa, ok, oj);
-      body_f4(acc, ea, ek, ej, std::true_type{});
-      if (st + 2 < e_whole) load(st + 2, ea, ek, ej);
-      body_f4(acc, oa, ok, oj, std::true_type{});
-    }
-    if (st < e_whole) body_f4(acc, ea, ek, ej, std::true_type{});
-    if (n_whole >= s_begin && n_whole < s_end) {
-      const int64_t kb = n_whole * 64 + 16 * g;
-      u4 xa[4], xk[4], xj;
+    } else {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        xa[m] = load_fields64(pa[m] - 16 * g, kb, a.n_f);
-        xk[m] = load_fields64(pk[m] - 16 * g, kb, a.n_f);
+        xa[m] = load_fields64(pa[m] - 16 * g, kb + 16 * g, a.n_f);
+        xk[m] = load_fields64(pk[m] - 16 * g, kb + 16 * g, a.n_f);
       }
-      xj = load_fields64(pj - 16 * g, kb, a.n_f);
-      body_f4(acc, xa, xk, xj, std::false_type{});
+      xj = load_fields64(pj - 16 * g, kb + 16 * g, a.n_f);
     }
-  } else {
-    for (int64_t st = s_begin; st < s_end; ++st) {
-      const int64_t kb = st * 64;
-      const bool full = (kb + 64) * 4 <= a.n_f;
-      u4 xa[4], xk[4], xj;
-      if (full) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          xa[m] = *reinterpret_cast<const u4*>(pa[m] + kb);
-          xk[m] = *reinterpret_cast<const u4*>(pk[m] + kb);
-        }
-        xj = *reinterpret_cast<const u4*>(pj + kb);
-      } else {
+    for (int s = 0; s < 4; ++s) {
+      unsigned cj[4], sel1[4];
+      codes4(word_of(xj, s), cj);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          xa[m] = load_fields64(pa[m] - 16 * g, kb + 16 * g, a.n_f);
-          xk[m] = load_fields64(pk[m] - 16 * g, kb + 16 * g, a.n_f);
-        }
-        xj = load_fields64(pj - 16 * g, kb + 16 * g, a.n_f);
-      }
+      for (int t = 0; t < 4; ++t) sel1[t] = __builtin_amdgcn_perm(0u, kSelJ1, cj[t]);
+      v4i A1[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        unsigned cj[4], sel1[4];
-        codes4(word_of(xj, s), cj);
+      for (int m = 0; m < 4; ++m) A1[m] = tile2::unpack16_rho1(word_of(xa[m], s));
 #pragma unroll
-        for (int t = 0; t < 4; ++t) sel1[t] = __builtin_amdgcn_perm(0u, kSelJ1, cj[t]);
-        v4i A1[4];
+      for (int c = 0; c < 4; ++c) {
+        unsigned ck[4];
+        codes4(word_of(xk[c], s), ck);
+        v4i M;  // rho_j(1) rho_k(1)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) A1[m] = tile2::unpack16_rho1(word_of(xa[m], s));
+        for (int t = 0; t < 4; ++t)
+          M[t] = (int)__builtin_amdgcn_perm(kRho1Twice, kRho1Table, ck[t] | sel1[t]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          unsigned ck[4];
-          codes4(word_of(xk[c], s), ck);
-          v4i M;  // rho_j(1) rho_k(1)
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            M[t] = (int)__builtin_amdgcn_perm(kRho1Twice, kRho1Table, ck[t] | sel1[t]);
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-            acc[m][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[m], M, acc[m][c], 0, 0, 0);
-        }
+        for (int m = 0; m < 4; ++m)
+          acc[m][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[m], M, acc[m][c], 0, 0, 0);
       }
     }
   }
@@ -647,15 +433,7 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if constexpr (F4) {
-        const v4f x = acc[m][c];
-        part[wave][4 * m + c][lane] = v4i{tile2::f4_count(x[0]), tile2::f4_count(x[1]),
-                                          tile2::f4_count(x[2]), tile2::f4_count(x[3])};
-      } else {
-        part[wave][4 * m + c][lane] = acc[m][c];
-      }
-    }
+    for (int c = 0; c < 4; ++c) part[wave][4 * m + c][lane] = acc[m][c];
   __syncthreads();
 
   v4i xyz[4];
@@ -664,8 +442,7 @@ __device__ __forceinline__ void complete_unit(const Triple3Args& a, int64_t j, i
     xyz[c] = part[0][4 * wave + c][lane] + part[1][4 * wave + c][lane] +
              part[2][4 * wave + c][lane] + part[3][4 * wave + c][lane];
   }
-  if constexpr (F4) __syncthreads();  // every wave's sums are read: part[wave] stages its stores
-  complete_block_row<F4>(a, j, i0 + 16 * wave, k0, xyz, reinterpret_cast<u4*>(&part[wave][0][0]));
+  complete_block_row<false>(a, j, i0 + 16 * wave, k0, xyz, nullptr);
 }
 
 // Middle vectors per unit of the complete-data kernel: one per wave.
@@ -1072,17 +849,13 @@ __global__ __launch_bounds__(1024) void complete3_flag_kernel(const int32_t* __r
   if (threadIdx.x == 0) *flag = ok ? 1 : 0;
 }
 
-template <bool F4>
+// The int8 form over one-j units: 2 x 2 waves over a 64 x 64 (i, k) tile
+// for one middle vector j; a unit whose rows are all complete computes its
+// tile together in the one-plane form (complete_unit).
 __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid ug,
                                                        const int64_t* __restrict__ offs,
                                                        int64_t unit_base, int64_t count) {
-  // 64 KB: the complete-data partial tiles, or else the workgroup's two fp4
-  // stage buffers of 2 WI + 2 WK + 1 row blocks and each wave's 6 KB of
-  // store staging
-  __shared__ v4i part[4][16][64];
-  static_assert(sizeof(part) >= (2 * (2 * WI + 2 * WK + 1) * 64 + 4 * 384) * sizeof(u4),
-                "stage buffers fit");
-  if (a.complete && *a.complete) return;  // uniform: mfma3_complete_kernel covers the call
+  __shared__ v4i part[4][16][64];  // 64 KB: the complete-data partial tiles
   const int wave = threadIdx.x >> 6;
   const int64_t n = a.n;
   const int64_t u = unit_base + xcd_unit(blockIdx.x, count);
@@ -1097,7 +870,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid u
     r = r < n ? r : n - 1;
     const bool ok = reinterpret_cast<const v4i*>(a.counts)[r].z == a.n_f;
     if (__syncthreads_and(ok ? 1 : 0)) {
-      complete_unit<F4>(a, j, it * BI, kt * BK, part);
+      complete_unit(a, j, it * BI, kt * BK, part);
       return;
     }
   }
@@ -1105,8 +878,8 @@ __global__ __launch_bounds__(256, 2) void mfma3_kernel(Triple3Args a, UnitGrid u
   const int64_t row0 = it * BI + (wave & 1) * 16 * WI;  // i range of this wave
   const int64_t col0 = kt * BK + (wave >> 1) * 16 * WK; // k range of this wave
   const bool active = !(row0 >= j || col0 + 16 * WK - 1 <= j || col0 >= n);
-  if (!F4 && !active) return;
-  general_wave<F4>(a, j, row0, col0, active, reinterpret_cast<u4*>(&part[0][0][0]));
+  if (!active) return;
+  general_wave(a, j, row0, col0, active);
 }
 
 // G[r][c] = sum_q rho_{g0+r,q}(1) rho_{g0+c,q}(1) for r, c < ng: the pair
@@ -1172,7 +945,7 @@ hipError_t launch_mfma3(const Triple3Args& a, hipStream_t stream) {
   }
   if (e == hipSuccess)
     e = a.f4 ? launch_units(mfma3_run_kernel, a, kRunTile, nullptr, stream, kJRun, a.offs_gen)
-             : launch_units(mfma3_kernel<false>, a, BI, nullptr, stream);
+             : launch_units(mfma3_kernel, a, BI, nullptr, stream);
   timing_end(stream);
   return e;
 }
