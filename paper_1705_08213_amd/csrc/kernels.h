@@ -164,15 +164,16 @@ __host__ __device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t count) {
 // column.  (A rectangle keeps the row-major order, which measured faster.)
 constexpr int64_t kStripRows = 8;
 
-// Triangle: square t of the squares (I, J), s0 <= I < s1, I <= J < T.  A
-// strip of h rows r0 .. r1 - 1 holds h (h - 1) / 2 squares in its first
-// h - 1 columns (column r0 + c has c + 1) and h in each of the T - r1 + 1
-// columns after them; the strips before the last are full, so the squares
-// before strip k number k A - H^2 k (k + 1) / 2 with
-// A = H (H - 1) / 2 + H (T - s0 + 1), H = kStripRows.
+// Triangle: square t of the squares (I, J), s0 <= I < s1, I <= J < T, in
+// strips of H square rows.  A strip of h rows r0 .. r1 - 1 holds
+// h (h - 1) / 2 squares in its first h - 1 columns (column r0 + c has c + 1)
+// and h in each of the T - r1 + 1 columns after them; the strips before the
+// last are full, so the squares before strip k number
+// k A - H^2 k (k + 1) / 2 with A = H (H - 1) / 2 + H (T - s0 + 1).
 __host__ __device__ inline void strip_square(int64_t t, int64_t T, int64_t s0, int64_t s1,
-                                             int64_t& I, int64_t& J) {
-  const int64_t H = kStripRows, nstrips = (s1 - s0 + H - 1) / H;
+                                             int64_t& I, int64_t& J,
+                                             int64_t H = kStripRows) {
+  const int64_t nstrips = (s1 - s0 + H - 1) / H;
   const int64_t A = H * (H - 1) / 2 + H * (T - s0 + 1);
   auto before = [&](int64_t k) { return k * A - H * H * k * (k + 1) / 2; };
   const double bq = (double)A - 0.5 * (double)(H * H);

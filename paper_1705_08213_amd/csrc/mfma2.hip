@@ -24,8 +24,8 @@ __global__ __launch_bounds__(1024) void complete_flag_kernel(const int32_t* __re
 }
 
 // Workgroup tile (I, J) of `b` in a grid of tiles of BM x BN pairs
-// (triangle: BM / BN tiles per square, squares in strip order).
-template <int BM, int BN>
+// (triangle: BM / BN tiles per square, squares in strips of H square rows).
+template <int BM, int BN, int H = kStripRows>
 __device__ __forceinline__ void tile_of(const Pair2Args& a, int64_t b, int64_t tiles_side,
                                         int64_t tiles_n, int64_t& I, int64_t& J) {
   constexpr int HALVES = BM / BN;
@@ -33,7 +33,7 @@ __device__ __forceinline__ void tile_of(const Pair2Args& a, int64_t b, int64_t t
   if (a.tri) {
     int64_t sq_i, sq_j;
     strip_square(b / HALVES, tiles_side, a.row_begin / BM, (a.row_end + BM - 1) / BM, sq_i,
-                 sq_j);
+                 sq_j, H);
     I = sq_i;
     J = HALVES * sq_j + b % HALVES;
   } else {
@@ -41,6 +41,10 @@ __device__ __forceinline__ void tile_of(const Pair2Args& a, int64_t b, int64_t t
     J = b % tiles_n;
   }
 }
+
+// Square rows per strip of the complete-data kernel's triangle order: its
+// squares are twice the height of the general kernel's.
+constexpr int kCompleteStripRows = 4;
 
 // Calls whose every row is complete: 2 x 2 waves of (16 WM) x (16 WN) pairs
 // (mfma2_complete_wave_tile); a workgroup exits at once when the flag says
@@ -53,7 +57,8 @@ __global__ __launch_bounds__(256, 2) void mfma2_complete_kernel(Pair2Args a,
   constexpr int BM = 32 * WM, BN = 32 * WN, NB = 2 * WM + 2 * WN;
   const int wave = threadIdx.x >> 6;
   int64_t I, J;
-  tile_of<BM, BN>(a, xcd_unit(blockIdx.x, gridDim.x), tiles_side, tiles_n, I, J);
+  tile_of<BM, BN, kCompleteStripRows>(a, xcd_unit(blockIdx.x, gridDim.x), tiles_side, tiles_n, I,
+                                      J);
   __shared__ u4 stage[2][NB][64];
   __shared__ u4 outs[4][128];
   tile2::mfma2_complete_wave_tile<WM, WN, F4>(a, I * BM + (wave & 1) * 16 * WM,
