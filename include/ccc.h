@@ -286,10 +286,11 @@ int ccc_2way_multi(const uint8_t* v, int64_t n_v, int64_t n_f, int64_t ld, int s
  * complete-data Gram matrix) lives in a fixed device array of
  * CCC_NOALLOC_SCRATCH_BYTES per device, kept until the process ends, instead
  * of the library workspace.  CCC_ERR_RANGE when the unit offsets (8 bytes per
- * pair of 64-row tiles, about n_v^2 / 1024 bytes) plus the counts (16 bytes
- * per vector when `counts` is NULL) exceed it.  The Gram matrix (4 n_v^2
- * bytes) is used only when it also fits (n_v up to about 2500); otherwise
- * every unit takes the general form, with the same results.  Every call on a
+ * tile pair of each of three unit grids: two of 64-row tiles and one of
+ * 32-row tiles, about 3 n_v^2 / 512 bytes in all) plus the counts (16 bytes
+ * per vector when `counts` is NULL) exceed it, about n_v > 64,000.  The Gram
+ * matrix (4 n_v^2 bytes) is used only when it also fits (n_v up to about
+ * 2500); otherwise every unit takes the general form, with the same results.  Every call on a
  * device shares that device's array: calls whose work overlaps on one device
  * (two streams, or two host threads) race and give undefined results; the
  * caller must order them.  The first call on a device looks up the array's

@@ -160,8 +160,9 @@ def test_range_limits():
 
 def test_noalloc_3way_validation_and_scratch_limit():
     """The no-allocation 3-way entry point validates like ccc_3way, and a
-    problem whose work-unit offsets (8 bytes per pair of 64-row tiles) cannot
-    fit its fixed scratch is a range error, caught before any HIP call."""
+    problem whose work-unit offsets (8 bytes per tile pair of two grids of
+    64-row tiles and one of 32-row tiles) cannot fit its fixed scratch is a
+    range error, caught before any HIP call."""
     big = I32MAX // 8 + 1
     assert call3n(n_f=big, ld=(big + 3) // 4 // 16 * 16 + 16) == ccc.CCC_ERR_RANGE
     assert call3n(ld=(1 << 28) + 16) == ccc.CCC_ERR_RANGE
@@ -169,6 +170,8 @@ def test_noalloc_3way_validation_and_scratch_limit():
     # 400000 rows: 6250 tiles, about 19.5 million tile pairs, 156 MB of offsets
     assert call3n(n_v=400000) == ccc.CCC_ERR_RANGE
     assert call3n(n_v=400000, counts=FAKE) == ccc.CCC_ERR_RANGE
+    # 70000 rows: 1094 tiles of 64 rows and 2188 of 32 per side, 28.7 MB of offsets
+    assert call3n(n_v=70000, counts=FAKE) == ccc.CCC_ERR_RANGE
     assert call3n(v=None, n_v=0) == ccc.CCC_OK
     assert call3n(n_v=2, tables=None, cc=None) == ccc.CCC_OK
 
