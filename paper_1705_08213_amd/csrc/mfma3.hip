@@ -637,20 +637,27 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
 // of the whole 32 x 32 (i, k) tile for its j over every field (2 x 2 blocks
 // x 8 planes of accumulators).  The rho(1) and P planes of the unit's 2 i
 // and 2 k blocks do not depend on j: per super-step the rows travel through
-// the workgroup's LDS stage once (`raw`: 2 i blocks, 2 k blocks, and one
-// block of the run's j rows, lane l the row j0 + min(l & 15, jn - 1)), wave
-// w turns row block w into its two planes and writes them to `planes`, and
-// every wave reads all four back; only j's masks and the modulation of the
-// k planes by D_j and P_j are each wave's own.  The steps are skewed by one
-// as in mfma3_complete_kernel, so one barrier per step covers both buffers.
+// the workgroup's LDS stage once (`raw`, wave w copying row block w: 2 i
+// blocks, 2 k blocks), wave w turns row block w into its two planes and
+// writes them to `planes`, and every wave reads all four back; only j's
+// masks and the modulation of the k planes by D_j and P_j are each wave's
+// own.  The steps are skewed by one as in mfma3_complete_kernel, so one
+// barrier per step covers both buffers.
+//
+// j's masks are the same for the 16 lanes of a field group, so a wave makes
+// them eight steps at a time: lane (g, l) turns the 32 fields of half l & 1
+// of step 8b + (l >> 1) in group g into their masks and writes them to the
+// wave's part of `jm`, and each half step reads its masks back (the 16
+// lanes of a group read one address).  The words of batch b + 1 are loaded
+// while batch b is multiplied.
 __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGrid ug,
                                                            const int64_t* __restrict__ offs,
                                                            int64_t unit_base, int64_t count) {
 #pragma clang fp contract(off)
   if (a.complete && *a.complete) return;  // uniform: mfma3_complete_kernel covers the call
-  constexpr int NB = 5, BPW = 2;  // raw row blocks per step; copies per wave (3 idle slots)
-  __shared__ u4 raw[2][NB][64];            // 10 KB
-  __shared__ u4 planes[2][4][2][2][64];    // 32 KB: [step & 1][block][half][rho(1), P][lane]
+  __shared__ u4 raw[2][4][64];            // 8 KB: [step & 1][row block][lane]
+  __shared__ u4 planes[2][4][2][2][64];   // 32 KB: [step & 1][block][half][rho(1), P][lane]
+  __shared__ u4 jm[4][4][16][3];          // 12 KB: [wave][group][half step][y, sg, p]
   const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
   const int64_t n = a.n;
@@ -663,34 +670,21 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
   const bool active = wave < jn;
   const int64_t i0 = it * kRunTile, k0 = kt * kRunTile;
 
-  // Copies: blocks 0-1 rows i, 2-3 rows k, 4 the run's j rows; a
+  // Copies: wave w copies row block w (0-1 rows i, 2-3 rows k) from a
   // wave-uniform base (the block's first row, clamped) plus a 32-bit lane
   // offset (r - rf < 16 rows of at most 2^28 bytes).
-  gbytes base[BPW];
-  uint32_t off[BPW];
-#pragma unroll
-  for (int t = 0; t < BPW; ++t) {
-    const int b = BPW * wave + t < NB ? BPW * wave + t : NB - 1;
-    int64_t r0, r1;
-    if (b < 4) {
-      r0 = (b < 2 ? i0 + 16 * b : k0 + 16 * (b - 2));
-      r1 = r0 + rl;
-    } else {
-      r0 = j0;
-      r1 = j0 + (rl < jn ? rl : jn - 1);
-    }
-    const int64_t rf = r0 < n ? r0 : n - 1, r = r1 < n ? r1 : n - 1;
+  gbytes base;
+  uint32_t off;
+  {
+    const int64_t r0 = wave < 2 ? i0 + 16 * wave : k0 + 16 * (wave - 2);
+    const int64_t rf = r0 < n ? r0 : n - 1, r = r0 + rl < n ? r0 + rl : n - 1;
     const uint64_t bp = (uint64_t)(a.v + rf * a.ld);
-    base[t] = (gbytes)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32)) << 32) |
-                       (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
-    off[t] = (uint32_t)((r - rf) * a.ld + 16 * g);
+    base = (gbytes)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bp >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)bp));
+    off = (uint32_t)((r - rf) * a.ld + 16 * g);
   }
   auto issue = [&](int64_t st, int buf) {
-#pragma unroll
-    for (int t = 0; t < BPW; ++t)
-      if (BPW * wave + t < NB)
-        tile2::stage_row((const uint8_t*)(base[t] + st * 64 + off[t]),
-                         &raw[buf][BPW * wave + t][0]);
+    tile2::stage_row((const uint8_t*)(base + st * 64 + off), &raw[buf][wave][0]);
   };
   // the planes of one row block's 16 bytes: per half, rho(1) and P
   auto planes_of = [](const u4& x, int h, u4& R, u4& P) {
@@ -700,14 +694,14 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
     P = u4{p0[0], p0[1], p1[0], p1[1]};
   };
   // this wave's share: row block `wave` (0-1 rows i, 2-3 rows k), both halves
-  auto build = [&](int rbuf, int pbuf) {
-    const u4 x = raw[rbuf][wave][lane];
+  auto build = [&](int buf) {
+    const u4 x = raw[buf][wave][lane];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       u4 R, P;
       planes_of(x, h, R, P);
-      planes[pbuf][wave][h][0][lane] = R;
-      planes[pbuf][wave][h][1][lane] = P;
+      planes[buf][wave][h][0][lane] = R;
+      planes[buf][wave][h][1][lane] = P;
     }
   };
 
@@ -720,21 +714,20 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
       for (int e = 0; e < 8; ++e) acc[m][c][e] = v4f{0, 0, 0, 0};
   auto as_v8 = [](const u4& x) { return v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0}; };
   // the MFMAs of one half super-step: planes of rows i (AR, AP) and k (KR,
-  // KP), j's two words
+  // KP), j's masks
   auto multiply = [&](const u4 (&AR)[2], const u4 (&AP)[2], const u4 (&KR)[2], const u4 (&KP)[2],
-                      unsigned wj0, unsigned wj1) {
-    unsigned y[4], sg[4], pm[4];
-    j_masks32_f4(wj0, wj1, y, sg, pm);
+                      const u4& y, const u4& sg, const u4& pm) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       v8i B[4];  // y z = D R, D P, P R, P P
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const unsigned R = word_of(KR[c], q), P = word_of(KP[c], q);
-        B[0][q] = (int)mod_d(R, y[q], sg[q]);
-        B[1][q] = (int)mod_d(P, y[q], sg[q]);
-        B[2][q] = (int)(R & pm[q]);
-        B[3][q] = (int)(P & pm[q]);
+        const unsigned yq = word_of(y, q), sq = word_of(sg, q), pq = word_of(pm, q);
+        B[0][q] = (int)mod_d(R, yq, sq);
+        B[1][q] = (int)mod_d(P, yq, sq);
+        B[2][q] = (int)(R & pq);
+        B[3][q] = (int)(P & pq);
       }
 #pragma unroll
       for (int yz = 0; yz < 4; ++yz)
@@ -751,26 +744,55 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
       }
     }
   };
+  // j's masks of two packed words (even and odd fields of 16 each)
+  auto masks_of = [](unsigned w0, unsigned w1, u4& y, u4& sg, u4& pm) {
+    unsigned yy[4], ss[4], pp[4];
+    j_masks32_f4(w0, w1, yy, ss, pp);
+    y = u4{yy[0], yy[1], yy[2], yy[3]};
+    sg = u4{ss[0], ss[1], ss[2], ss[3]};
+    pm = u4{pp[0], pp[1], pp[2], pp[3]};
+  };
 
   const int64_t nfull = a.n_f / 256;
-  u4 xj = u4{0, 0, 0, 0};  // this wave's j word of the step to multiply next
+  // this lane's two words of j's batch of eight steps from st0 (zero past
+  // the whole steps); the wave's row j from a uniform base
+  const uint64_t jp = (uint64_t)(a.v + j * a.ld);
+  const gbytes jrow = (gbytes)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(jp >> 32))
+                                << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)jp));
+  const uint32_t joff = (uint32_t)(64 * (rl >> 1) + 16 * g + 8 * (rl & 1));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  auto jwords = [&](int64_t st0) {
+    u2 w = u2{0u, 0u};
+    if (st0 + (rl >> 1) < nfull)
+      w = *reinterpret_cast<const __attribute__((address_space(1))) u2*>(jrow + st0 * 64 + joff);
+    return w;
+  };
+  u2 jw = u2{0u, 0u};
   if (nfull > 0) {
     issue(0, 0);
     if (nfull > 1) issue(1, 1);
+    if (active) jw = jwords(0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    build(0, 0);
-    xj = raw[0][4][16 * g + wave];
+    build(0);
   }
   for (int64_t st = 0; st < nfull; ++st) {
     const int buf = (int)(st & 1);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // raw(st + 1) of this wave has landed
     __syncthreads();  // every wave's has; planes(st) are written; step st - 1's buffers are free
-    const u4 xj_now = xj;
+    if (active && (st & 7) == 0) {  // uniform: the masks of steps st .. st + 7
+      u4 y, sg, pm;
+      masks_of(jw.x, jw.y, y, sg, pm);
+      u4* d = &jm[wave][g][rl][0];
+      d[0] = y;
+      d[1] = sg;
+      d[2] = pm;
+      jw = jwords(st + 8);
+    }
     if (st + 1 < nfull) {
-      xj = raw[buf ^ 1][4][16 * g + wave];
       if (st + 2 < nfull) issue(st + 2, buf);
-      build(buf ^ 1, buf ^ 1);
+      build(buf ^ 1);
     }
     if (active) {
 #pragma unroll
@@ -783,7 +805,8 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
           KR[m] = planes[buf][2 + m][h][0][lane];
           KP[m] = planes[buf][2 + m][h][1][lane];
         }
-        multiply(AR, AP, KR, KP, word_of(xj_now, 2 * h), word_of(xj_now, 2 * h + 1));
+        const u4* ms = &jm[wave][g][2 * (st & 7) + h][0];
+        multiply(AR, AP, KR, KP, ms[0], ms[1], ms[2]);
       }
     }
   }
@@ -804,7 +827,9 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
         planes_of(xr[m], h, AR[m], AP[m]);
         planes_of(xr[2 + m], h, KR[m], KP[m]);
       }
-      multiply(AR, AP, KR, KP, word_of(xt, 2 * h), word_of(xt, 2 * h + 1));
+      u4 y, sg, pm;
+      masks_of(word_of(xt, 2 * h), word_of(xt, 2 * h + 1), y, sg, pm);
+      multiply(AR, AP, KR, KP, y, sg, pm);
     }
   }
   __syncthreads();  // every wave is done with `planes`: it now stages the stores

@@ -107,9 +107,10 @@ __device__ __forceinline__ void emit_triple_staged(const Triple3Args& a, bool va
   valid = valid && i >= a.i_begin && i < a.i_end;
   const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
   const unsigned gm = (unsigned)(__ballot(valid ? 1 : 0) >> (16 * g)) & 0xFFFFu;
-  const int64_t p = valid ? triple_index(a.n, i, j, k) - a.t_base - rl : 0;
-  const int first = gm ? __ffs(gm) - 1 : 0;
-  const int64_t p0 = __shfl(p, 16 * g + first);  // entry of the group's lane 0 (may be unused)
+  // entry of the group's lane 0 (unused when no triple of the group is
+  // valid): T(i, j, k) is affine in k, so it follows from that lane's k
+  // whether or not its own triple is valid
+  const int64_t p0 = triple_index(a.n, i, j, k - rl) - a.t_base;
   u4* T = scratch + 32 * g;        // 16 tables of the group: 32 x 16 B
   u4* C = scratch + 128 + 64 * g;  // 16 CCC rows: 64 x 16 B
   if (a.tables) {
