@@ -715,14 +715,14 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
   auto as_v8 = [](const u4& x) { return v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0}; };
   // the MFMAs of one half super-step: planes of rows i (AR, AP) and k (KR,
   // KP), j's masks
-  auto multiply = [&](const u4 (&AR)[2], const u4 (&AP)[2], const u4 (&KR)[2], const u4 (&KP)[2],
-                      const u4& y, const u4& sg, const u4& pm) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
+  auto multiply_c = [&](const u4 (&AR)[2], const u4 (&AP)[2], const u4& KRc, const u4& KPc,
+                        const u4& y, const u4& sg, const u4& pm, auto cc) {
+    constexpr int c = decltype(cc)::value;
+    {
       v8i B[4];  // y z = D R, D P, P R, P P
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const unsigned R = word_of(KR[c], q), P = word_of(KP[c], q);
+        const unsigned R = word_of(KRc, q), P = word_of(KPc, q);
         const unsigned yq = word_of(y, q), sq = word_of(sg, q), pq = word_of(pm, q);
         B[0][q] = (int)mod_d(R, yq, sq);
         B[1][q] = (int)mod_d(P, yq, sq);
@@ -743,6 +743,11 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
         }
       }
     }
+  };
+  auto multiply = [&](const u4 (&AR)[2], const u4 (&AP)[2], const u4 (&KR)[2], const u4 (&KP)[2],
+                      const u4& y, const u4& sg, const u4& pm) {
+    multiply_c(AR, AP, KR[0], KP[0], y, sg, pm, std::integral_constant<int, 0>{});
+    multiply_c(AR, AP, KR[1], KP[1], y, sg, pm, std::integral_constant<int, 1>{});
   };
   // j's masks of two packed words (even and odd fields of 16 each)
   auto masks_of = [](unsigned w0, unsigned w1, u4& y, u4& sg, u4& pm) {
@@ -795,19 +800,32 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
       build(buf ^ 1);
     }
     if (active) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        u4 AR[2], AP[2], KR[2], KP[2];
+      // The second half's operands are read while the first half's first
+      // block column is multiplied, so that their LDS latency hides behind
+      // MFMAs (the fences keep the compiler to this order).
+      u4 AR[2][2], AP[2][2], KR[2][2], KP[2][2], M[2][3];
+      auto read_half = [&](int h) {
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-          AR[m] = planes[buf][m][h][0][lane];
-          AP[m] = planes[buf][m][h][1][lane];
-          KR[m] = planes[buf][2 + m][h][0][lane];
-          KP[m] = planes[buf][2 + m][h][1][lane];
+          AR[h][m] = planes[buf][m][h][0][lane];
+          AP[h][m] = planes[buf][m][h][1][lane];
+          KR[h][m] = planes[buf][2 + m][h][0][lane];
+          KP[h][m] = planes[buf][2 + m][h][1][lane];
         }
         const u4* ms = &jm[wave][g][2 * (st & 7) + h][0];
-        multiply(AR, AP, KR, KP, ms[0], ms[1], ms[2]);
-      }
+#pragma unroll
+        for (int x = 0; x < 3; ++x) M[h][x] = ms[x];
+      };
+      read_half(0);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply_c(AR[0], AP[0], KR[0][0], KP[0][0], M[0][0], M[0][1], M[0][2],
+                 std::integral_constant<int, 0>{});
+      __builtin_amdgcn_sched_barrier(0);
+      read_half(1);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply_c(AR[0], AP[0], KR[0][1], KP[0][1], M[0][0], M[0][1], M[0][2],
+                 std::integral_constant<int, 1>{});
+      multiply(AR[1], AP[1], KR[1], KP[1], M[1][0], M[1][1], M[1][2]);
     }
   }
   if (nfull * 256 < a.n_f && active) {  // the padded last step: plain loads, all four blocks
