@@ -694,8 +694,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
     P = u4{p0[0], p0[1], p1[0], p1[1]};
   };
   // this wave's share: row block `wave` (0-1 rows i, 2-3 rows k), both halves
-  auto build = [&](int buf) {
-    const u4 x = raw[buf][wave][lane];
+  auto build_from = [&](const u4& x, int buf) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       u4 R, P;
@@ -704,6 +703,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
       planes[buf][wave][h][1][lane] = P;
     }
   };
+  auto build = [&](int buf) { build_from(raw[buf][wave][lane], buf); };
 
   v4f acc[2][2][8];
 #pragma unroll
@@ -795,14 +795,19 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
       d[2] = pm;
       jw = jwords(st + 8);
     }
-    if (st + 1 < nfull) {
-      if (st + 2 < nfull) issue(st + 2, buf);
-      build(buf ^ 1);
-    }
-    if (active) {
-      // The second half's operands are read while the first half's first
-      // block column is multiplied, so that their LDS latency hides behind
-      // MFMAs (the fences keep the compiler to this order).
+    const bool more = st + 1 < nfull;  // uniform
+    if (more && st + 2 < nfull) issue(st + 2, buf);
+    if (!active) {
+      if (more) build(buf ^ 1);
+    } else {
+      // Every LDS read of the step goes out ahead of the MFMAs that need it:
+      // the next step's row block and the first half's operands, then the
+      // second half's while the first half's first block column is
+      // multiplied (the fences keep the compiler to this order).  The next
+      // step's planes are built between the two halves; on the last step
+      // the build reads and writes buffers that no wave uses any more (no
+      // branch, so that the compiler keeps the MFMAs where they are).
+      const u4 xn = raw[buf ^ 1][wave][lane];
       u4 AR[2][2], AP[2][2], KR[2][2], KP[2][2], M[2][3];
       auto read_half = [&](int h) {
 #pragma unroll
@@ -825,6 +830,7 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
       __builtin_amdgcn_sched_barrier(0);
       multiply_c(AR[0], AP[0], KR[0][1], KP[0][1], M[0][0], M[0][1], M[0][2],
                  std::integral_constant<int, 1>{});
+      build_from(xn, buf ^ 1);
       multiply(AR[1], AP[1], KR[1], KP[1], M[1][0], M[1][1], M[1][2]);
     }
   }
