@@ -612,21 +612,89 @@ __global__ __launch_bounds__(256, 3) void mfma3_complete_kernel(Triple3Args a, U
       multiply(A, K, word_of(xt, 2 * h), word_of(xt, 2 * h + 1));
     }
   }
-  __syncthreads();  // every wave is done with `planes`: it now stages the stores
+  __syncthreads();  // every wave is done with `raw` and `planes`
+
+  // The epilogue's inputs are read before any of its stores (a wait for a
+  // load also waits for every store issued before it): the unit's Gram tile
+  // G[i][k] into `raw` (one copy for the four waves), each wave's rows i
+  // (their count n(1), G[i][j] and factors) into its 2 KB past the store
+  // staging in `planes`, and its columns k and j into registers.
+  const v4i* cnt = reinterpret_cast<const v4i*>(a.counts);
+  const int64_t ng = a.ng, g0 = a.g0;
+  int32_t(*gt)[64] = reinterpret_cast<int32_t(*)[64]>(&raw[0][0][0]);  // 16 KB of the 18
+  {
+    const int r = threadIdx.x >> 2, q = threadIdx.x & 3;  // row r, columns 16q ..
+    const int64_t ir = (i0 + r < n ? i0 + r : n - 1) - g0;
+    const int32_t* grow = a.gram + ir * ng;
+    int32_t x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int64_t k = k0 + 16 * q + t;
+      x[t] = grow[(k < n ? k : n - 1) - g0];
+    }
+#pragma unroll
+    for (int t = 0; t < 16; t += 4)
+      *reinterpret_cast<v4i*>(&gt[r][16 * q + t]) = v4i{x[t], x[t + 1], x[t + 2], x[t + 3]};
+  }
+  struct RowIn {
+    double w[2];
+    int x, xy, pad0, pad1;
+  };
+  RowIn* rows = reinterpret_cast<RowIn*>(&planes[0][0][0][0] + 1536 + 128 * wave);  // 64 x 32 B
+  if (active) {
+    const int64_t i = i0 + lane, ii = i < n ? i : n - 1;
+    RowIn ri;
+    triple_factors(a, ii, ri.w);
+    ri.x = cnt[ii].y;
+    ri.xy = a.gram[(ii - g0) * ng + (j - g0)];
+    ri.pad0 = ri.pad1 = 0;
+    rows[lane] = ri;
+  }
+  const unsigned S8 = 8u * (unsigned)a.n_f, Y = (unsigned)cnt[j].y;
+  double wj[2], wk[4][2];
+  unsigned Z[4], YZ[4];
+  triple_factors(a, j, wj);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t k = k0 + 16 * c + rl;
+    const int64_t kk = k > j && k < n ? k : j;  // a valid row for invalid lanes
+    triple_factors(a, kk, wk[c]);
+    Z[c] = (unsigned)cnt[kk].y;
+    YZ[c] = (unsigned)a.gram[(j - g0) * ng + (kk - g0)];
+  }
+  __syncthreads();  // the Gram tile is in place
   if (!active) return;
 
-  // Epilogue: 4 block rows of 16 triples per lane for this wave's j.
+  // Epilogue: 4 block rows of 16 triples per lane for this wave's j
+  // (S_xyz = G[i][k] + the modulated sums; the other pair sums from the Gram
+  // matrix, the single counts from the 1-way counts).
   u4* outs = &planes[0][0][0][0] + 384 * wave;
   tile2::static_for<4>([&](auto mc) {
     constexpr int m = decltype(mc)::value;
-    v4i xyz[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const v4f x = acc[m][c];
-      xyz[c] = v4i{tile2::f4_count(x[0]), tile2::f4_count(x[1]), tile2::f4_count(x[2]),
-                   tile2::f4_count(x[3])};
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * m + 4 * g + e;
+      const int64_t i = i0 + r;
+      const RowIn ri = rows[r];
+      const unsigned X = (unsigned)ri.x, XY = (unsigned)ri.xy;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t k = k0 + 16 * c + rl;
+        const bool valid = k > j && k < n && i < j;
+        const unsigned XZ = (unsigned)gt[r][16 * c + rl];
+        const unsigned XYZ = XZ + (unsigned)tile2::f4_count(acc[m][c][e]);
+        int t[8];
+        t[7] = (int)XYZ;
+        t[6] = (int)(2u * XY - XYZ);
+        t[5] = (int)(2u * XZ - XYZ);
+        t[3] = (int)(2u * YZ[c] - XYZ);
+        t[4] = (int)(4u * X - 2u * XY - 2u * XZ + XYZ);
+        t[2] = (int)(4u * Y - 2u * XY - 2u * YZ[c] + XYZ);
+        t[1] = (int)(4u * Z[c] - 2u * XZ - 2u * YZ[c] + XYZ);
+        t[0] = (int)(S8 - 4u * (X + Y + Z[c]) + 2u * (XY + XZ + YZ[c]) - XYZ);
+        emit_triple_staged(a, valid, i, j, k, t, ri.w, wj, wk[c], outs);
+      }
     }
-    complete_block_row<true>(a, j, i0 + 16 * m, k0, xyz, outs);
   });
 }
 
