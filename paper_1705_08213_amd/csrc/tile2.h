@@ -807,7 +807,29 @@ __device__ __forceinline__ void mfma2_complete_wave_tile(const Pair2Args& a, int
       a, I0, J0, active, pa, pb, stage,
       [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) { body(xa, xb, std::true_type{}); },
       [&](const u4 (&xa)[WM], const u4 (&xb)[WN]) { body(xa, xb, std::false_type{}); });
+
+  // The epilogue's inputs are read before its first store (a wait for a
+  // load also waits for every store issued before it): the columns' into
+  // registers, the 16 WM rows' (n(1) and factors) into this wave's part of
+  // the stage, which every wave is done with after the barrier.
+  struct RowIn {
+    double w[2];
+    int n1, pad0, pad1, pad2;
+  };
+  static_assert(sizeof(RowIn) == 32, "two 16-byte halves");
+  static_assert(4 * 16 * WM * sizeof(RowIn) <= sizeof(u4) * (2 * WM + 2 * WN) * 64 * 2,
+                "the rows fit in the stage");
+  __syncthreads();
   if (!active) return;
+  RowIn* rows = reinterpret_cast<RowIn*>(&stage[0][0][0]) + 16 * WM * wave;
+  for (int t = lane; t < 16 * WM; t += 64) {
+    const int64_t i = row0 + t, ii = i < a.n_a ? i : a.n_a - 1;
+    RowIn ri;
+    side_factors(a, 0, ii, ri.w);
+    ri.n1 = reinterpret_cast<const v4i*>(a.counts_a)[ii].y;
+    ri.pad0 = ri.pad1 = ri.pad2 = 0;
+    rows[t] = ri;
+  }
 
   // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
   const int nf4 = (int)(4 * a.n_f);
@@ -824,9 +846,9 @@ __device__ __forceinline__ void mfma2_complete_wave_tile(const Pair2Args& a, int
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t i = row0 + 16 * m + 4 * g + e;
-      const int n1i = reinterpret_cast<const v4i*>(a.counts_a)[i < a.n_a ? i : a.n_a - 1].y;
-      double wi[2];
-      side_factors(a, 0, i, wi);
+      const RowIn ri = rows[16 * m + 4 * g + e];
+      const int n1i = ri.n1;
+      const double(&wi)[2] = ri.w;
 #pragma unroll
       for (int n = 0; n < WN; ++n) {
         const int64_t j = col0 + 16 * n + rl;
