@@ -691,35 +691,46 @@ __device__ __forceinline__ void mfma2_wave_tile(const Pair2Args& a, int64_t row0
   if (!active) return;
 
   // Epilogue: lane holds rows 4g + e (e = 0..3) of column rl of each 16x16 block.
+  // The factors and (fp4) this call's counts of the wave's 16 WM rows and
+  // 16 WN columns are read into its own LDS before the first store (a wait
+  // for a load also waits for every store issued before it).
+  struct SideIn {
+    double w[2];
+    v4i c;
+  };
+  static_assert(sizeof(SideIn) == 32, "two 16-byte halves");
+  __shared__ SideIn side_in[4][16 * (WM + WN)];
+  SideIn* rows = side_in[threadIdx.x >> 6];
+  for (int t = lane; t < 16 * (WM + WN); t += 64) {
+    const bool is_row = t < 16 * WM;
+    const int64_t x = is_row ? row0 + t : col0 + (t - 16 * WM);
+    const int64_t nx = is_row ? a.n_a : a.n_b;
+    SideIn si;
+    side_factors(a, is_row ? 0 : 1, x, si.w);
+    si.c = v4i{0, 0, 0, 0};
+    if constexpr (F4)
+      si.c = reinterpret_cast<const v4i*>(is_row ? a.chunk_a : a.chunk_b)[x < nx ? x : nx - 1];
+    rows[t] = si;
+  }
   const int kpad = (int)((a.n_f + 255) / 256 * 256);  // fields the fp4 loop covers
 #pragma unroll
   for (int m = 0; m < WM; ++m) {
-    double wi[4][2];
-    v4i ci[4];  // this call's counts of rows i (fp4 form)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t i = row0 + 16 * m + 4 * g + e;
-      side_factors(a, 0, i, wi[e]);
-      if constexpr (F4) ci[e] = reinterpret_cast<const v4i*>(a.chunk_a)[i < a.n_a ? i : a.n_a - 1];
-    }
 #pragma unroll
     for (int n = 0; n < WN; ++n) {
       const int64_t j = col0 + 16 * n + rl;
-      double wj[2];
-      side_factors(a, 1, j, wj);
-      v4i cj{0, 0, 0, 0};
-      if constexpr (F4) cj = reinterpret_cast<const v4i*>(a.chunk_b)[j < a.n_b ? j : a.n_b - 1];
+      const SideIn sj = rows[16 * WM + 16 * n + rl];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i = row0 + 16 * m + 4 * g + e;
+        const SideIn si = rows[16 * m + 4 * g + e];
         const bool valid = i < a.n_a && j < a.n_b && !(a.tri && i >= j);
         v4i t;
         if constexpr (F4)
           t = table_f4u(acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e],
-                        ci[e], cj, kpad);
+                        si.c, sj.c, kpad);
         else
           t = v4i{acc[m][n][0][e], acc[m][n][1][e], acc[m][n][2][e], acc[m][n][3][e]};
-        emit_pair(a, valid, i, j, t, wi[e], wj);
+        emit_pair(a, valid, i, j, t, si.w, sj.w);
       }
     }
   }
