@@ -928,8 +928,18 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
   if (!active) return;
 
   // Epilogue: entry 4a + 2b + c; lane holds rows i0 + 16m + 4g + e of column
-  // k0 + 16c + rl.
+  // k0 + 16c + rl.  Every factor is read before the first store (a wait for
+  // a load also waits for every store issued before it): the rows' into this
+  // wave's 512 bytes past the store staging in `planes`, the others' into
+  // registers.
   u4* outs = &planes[0][0][0][0][0] + 384 * wave;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2* wrow = reinterpret_cast<d2*>(&planes[0][0][0][0][0] + 1536) + 32 * wave;
+  if (lane < 32) {
+    double w[2];
+    triple_factors(a, i0 + lane, w);
+    wrow[lane] = d2{w[0], w[1]};
+  }
   double wj[2], wk[2][2];
   triple_factors(a, j, wj);
 #pragma unroll
@@ -939,8 +949,8 @@ __global__ __launch_bounds__(256, 2) void mfma3_run_kernel(Triple3Args a, UnitGr
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t i = i0 + 16 * m + 4 * g + e;
-      double wi[2];
-      triple_factors(a, i, wi);
+      const d2 wv = wrow[16 * m + 4 * g + e];
+      const double wi[2] = {wv.x, wv.y};
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int64_t k = k0 + 16 * c + rl;
